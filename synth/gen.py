@@ -1,0 +1,215 @@
+"""Seeded generators for sparse tensors shaped like the paper's workloads.
+
+Section 5.1 evaluates on rating tensors (users x items x time; values 1..5)
+and on synthetic tensors of order 3..10. Neither data set ships here; these
+generators stand in for them with the shapes, value ranges and skewed
+(Zipf) index distributions of such data.
+
+Every function takes an explicit seed or numpy Generator, so both the oracle
+and the GPU library receive identical inputs.
+"""
+from concurrent.futures import ThreadPoolExecutor
+from dataclasses import dataclass, field
+
+import numpy as np
+import pandas as pd
+
+_POOL = ThreadPoolExecutor(8)
+
+
+def _rng(seed):
+    return seed if isinstance(seed, np.random.Generator) else \
+        np.random.Generator(np.random.PCG64(seed))
+
+
+def _pack(idx, dims):
+    """Mixed-radix key of each coordinate tuple; exact in 128 bits, returned
+    as one uint64 when the key space fits, else as a structured pair."""
+    space = 1
+    for d in dims:
+        space *= int(d)
+    if space < 2 ** 63:
+        key = np.zeros(idx.shape[1], dtype=np.int64)
+        for n, d in enumerate(dims):
+            key = key * np.int64(d) + idx[n].astype(np.int64)
+        return key
+    # split the modes into two groups whose key spaces each fit in 63 bits
+    hi = np.zeros(idx.shape[1], dtype=np.int64)
+    lo = np.zeros(idx.shape[1], dtype=np.int64)
+    half = len(dims) // 2
+    for n, d in enumerate(dims):
+        if n < half:
+            hi = hi * np.int64(d) + idx[n].astype(np.int64)
+        else:
+            lo = lo * np.int64(d) + idx[n].astype(np.int64)
+    out = np.empty(idx.shape[1], dtype=[("hi", np.int64), ("lo", np.int64)])
+    out["hi"] = hi
+    out["lo"] = lo
+    return out
+
+
+def _first_distinct(idx, dims):
+    """Indices of the first occurrence of every distinct tuple, in draw
+    order (hash-based duplicate detection)."""
+    key = _pack(idx, dims)
+    if key.dtype.names:
+        dup = pd.DataFrame({"hi": key["hi"], "lo": key["lo"]}).duplicated(
+            keep="first").values
+    else:
+        dup = pd.Series(key).duplicated(keep="first").values
+    return np.flatnonzero(~dup)
+
+
+def uniform_distinct(seed, dims, count):
+    """count distinct coordinates drawn uniformly, kept in first-drawn order."""
+    rng = _rng(seed)
+    dims = [int(d) for d in dims]
+    space = int(np.prod(np.array(dims, dtype=object)))
+    if count > space:
+        raise ValueError("more nonzeros than cells")
+    idx = np.zeros((len(dims), 0), dtype=np.int32)
+    while idx.shape[1] < count:
+        need = count - idx.shape[1]
+        draw = np.stack([rng.integers(0, d, size=int(need * 1.2) + 16,
+                                      dtype=np.int32) for d in dims])
+        idx = np.concatenate([idx, draw], axis=1)
+        idx = idx[:, _first_distinct(idx, dims)]
+    return np.ascontiguousarray(idx[:, :count])
+
+
+class _Zipf:
+    """Inverse-CDF sampler of P(k) ~ k^-s over k = 1..I, mapped to row ids by a
+    seeded random relabelling so that hot rows are not adjacent."""
+
+    def __init__(self, rng, I, s):
+        w = np.arange(1, I + 1, dtype=np.float64) ** (-float(s))
+        self.cdf = np.cumsum(w)
+        self.cdf /= self.cdf[-1]
+        self.label = rng.permutation(I).astype(np.int32)
+
+    def draw(self, rng, size):
+        u = rng.random(size)
+        parts = list(_POOL.map(
+            lambda c: np.searchsorted(self.cdf, c, side="right"),
+            np.array_split(u, 16)))
+        k = np.concatenate(parts)
+        np.minimum(k, len(self.cdf) - 1, out=k)
+        return self.label[k]
+
+
+def zipf_distinct(seed, dims, s, count):
+    """count distinct coordinates with every mode's index drawn Zipf(s); the
+    tuples are deduplicated and redrawn until enough are distinct, kept in
+    first-drawn order."""
+    rng = _rng(seed)
+    dims = [int(d) for d in dims]
+    samplers = [_Zipf(rng, d, s) for d in dims]
+    idx = np.zeros((len(dims), 0), dtype=np.int32)
+    rounds = 0
+    ratio = 2.0
+    while idx.shape[1] < count:
+        have = idx.shape[1]
+        need = count - have
+        m = int(need * ratio) + 64
+        draw = np.stack([z.draw(rng, m) for z in samplers])
+        idx = np.concatenate([idx, draw], axis=1)
+        idx = idx[:, _first_distinct(idx, dims)]
+        gained = max(idx.shape[1] - have, 1)
+        ratio = min(64.0, 1.1 * m / gained)
+        rounds += 1
+        if rounds > 200:
+            raise RuntimeError("cannot draw enough distinct coordinates")
+    return np.ascontiguousarray(idx[:, :count])
+
+
+def planted_values(seed, dims, idx, J, R, a_std, b_std, scale=1.0,
+                   chunk=1 << 20):
+    """Values of a planted low-rank tensor at the coordinates idx.
+
+    Data synthesis only: draws planted matrices P^(n) (I_n x J) and
+    Q^(n) (J x R) with normal entries of the given standard deviations and
+    returns scale * sum_r prod_n (P^(n) Q^(n))[i_n, r] as float64. The values
+    are an input to both sides of every comparison; whether the structure is
+    truly low-rank is pinned by the planted-recovery test, not assumed.
+    """
+    rng = _rng(seed)
+    U = []
+    for d in dims:
+        P = rng.normal(0.0, a_std, size=(int(d), J))
+        Q = rng.normal(0.0, b_std, size=(J, R))
+        U.append((P @ Q).astype(np.float64))
+    nnz = idx.shape[1]
+    out = np.empty(nnz, dtype=np.float64)
+    for lo in range(0, nnz, chunk):
+        hi = min(nnz, lo + chunk)
+        prod = np.ones((hi - lo, R))
+        for n, u in enumerate(U):
+            prod *= u[idx[n, lo:hi]]
+        out[lo:hi] = prod.sum(axis=1) * scale
+    return out
+
+
+@dataclass
+class Tensor:
+    dims: list
+    train_idx: np.ndarray          # int32 (N, nnz_train)
+    train_val: np.ndarray          # float32 (nnz_train,)
+    test_idx: np.ndarray           # int32 (N, nnz_test)
+    test_val: np.ndarray           # float32 (nnz_test,)
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def order(self):
+        return len(self.dims)
+
+
+def make_tensor(w, seed=None):
+    """Build the synthetic tensor of a Workload (see configs.py)."""
+    seed = w.data_seed if seed is None else seed
+    rng = _rng(seed)
+    if w.index_dist == "uniform":
+        idx = uniform_distinct(rng, w.dims, w.nnz)
+    else:
+        idx = zipf_distinct(rng, w.dims, w.zipf_s, w.nnz)
+    x = planted_values(rng, w.dims, idx, w.planted_rank, w.planted_rank,
+                       w.planted_a_std, w.planted_b_std, w.planted_scale)
+    x = x + rng.normal(0.0, w.noise_std, size=x.shape)
+    if w.values == "rating":
+        x = np.clip(np.rint(w.rating_offset + x), 1.0, 5.0)
+    order = rng.permutation(w.nnz)
+    n_test = int(round(w.nnz * w.test_frac))
+    te, tr = order[:n_test], order[n_test:]
+    te.sort()
+    tr.sort()
+    return Tensor(dims=list(w.dims),
+                  train_idx=np.ascontiguousarray(idx[:, tr]),
+                  train_val=x[tr].astype(np.float32),
+                  test_idx=np.ascontiguousarray(idx[:, te]),
+                  test_val=x[te].astype(np.float32),
+                  meta={"workload": w.name, "seed": seed})
+
+
+def init_params(seed, dims, J, R, a_std, b_std=None, dist="normal"):
+    """Initial factor and core matrices as float32 (the starting point of
+    Algorithm 3). dist 'normal': N(0, std^2) entries; 'uniform': U(0, std)."""
+    rng = _rng(seed)
+    b_std = a_std if b_std is None else b_std
+    Js = [J] * len(dims) if np.isscalar(J) else list(J)
+    A, B = [], []
+    for d, j in zip(dims, Js):
+        if dist == "normal":
+            A.append(rng.normal(0.0, a_std, size=(int(d), j)).astype(np.float32))
+        else:
+            A.append(rng.uniform(0.0, a_std, size=(int(d), j)).astype(np.float32))
+    for j in Js:
+        if dist == "normal":
+            B.append(rng.normal(0.0, b_std, size=(j, R)).astype(np.float32))
+        else:
+            B.append(rng.uniform(0.0, b_std, size=(j, R)).astype(np.float32))
+    return A, B
+
+
+def epoch_perm(seed, epoch, nnz):
+    """Visiting order of the training set for one epoch (a permutation)."""
+    rng = _rng(np.random.SeedSequence([int(seed), int(epoch)]))
+    return rng.permutation(nnz).astype(np.int64)

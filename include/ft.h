@@ -1,0 +1,201 @@
+/*
+ * ft.h -- C ABI of the MI355X sparse FastTucker SGD library.
+ *
+ * The library implements the hot path of FastTuckerPlus (Li et al.,
+ * arXiv 2404.10087): the per-nonzero stochastic gradient sweep of sparse
+ * FastTucker decomposition, x_{i1..iN} ~ sum_r prod_n (a^(n)_{i_n,:} b^(n)_{:,r})
+ * (Eq. (3)), alternating a factor-matrix phase (Algorithm 3 first loop,
+ * update rule Eq. (12)) and a core-matrix phase (Algorithm 5: gradient
+ * accumulated over the training set, one update per epoch).
+ *
+ * General rules
+ *   - Every function returns ft_status and never aborts or throws.
+ *   - Arguments are validated on the host before any device work; a call that
+ *     fails validation returns FT_EINVAL (or FT_ESTATE) and changes nothing.
+ *     ft_last_error() then describes the failure.
+ *   - A handle lives on the HIP device that was current at ft_create and owns
+ *     all device memory it allocates. Calls on one handle are not thread-safe.
+ *   - Indices are 0-based int32; nonzero counts are int64.
+ *   - All pointers in this header are HOST pointers unless the comment says
+ *     "device". Input buffers are copied; the caller keeps ownership.
+ *   - The device path supports order 2..5, 1 <= J_n <= 32 and 1 <= R <= 32
+ *     (zero padding of J and R to the matrix-core tile is exact for order >= 2).
+ */
+#ifndef FT_H
+#define FT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ft_handle ft_handle;
+
+typedef enum {
+    FT_OK = 0,
+    FT_EINVAL = 1,      /* bad argument; nothing changed                    */
+    FT_ENOMEM = 2,      /* device or host allocation failed                 */
+    FT_EDEVICE = 3,     /* no usable HIP device, or a HIP runtime error     */
+    FT_ESTATE = 4,      /* call not valid in the handle's current state     */
+    FT_ENONFINITE = 5   /* an epoch produced a non-finite loss              */
+} ft_status;
+
+typedef enum { FT_TRAIN = 0, FT_TEST = 1 } ft_set;
+
+/* Arithmetic of the a.B contraction (the rest of the path is FP32; losses and
+ * RMSE are reduced in FP64). */
+typedef enum { FT_FP32 = 0, FT_BF16 = 1, FT_FP8_E4M3 = 2 } ft_precision;
+
+/* How a minibatch's summed row gradient is applied (Eq. (12) applied per
+ * sample, with duplicate rows of one minibatch combined):
+ *   FT_ROW_SUM  a <- a - lr_A * G      (gradient of the minibatch loss)
+ *   FT_ROW_MEAN a <- a - lr_A * G / k  (mean of the k per-sample steps)      */
+typedef enum { FT_ROW_SUM = 0, FT_ROW_MEAN = 1 } ft_row_scale;
+
+/* When the core matrices move: once per epoch with the gradient summed over
+ * the training set and divided by its size (Algorithm 5), or after every
+ * minibatch with that minibatch's mean gradient (Algorithm 3, Eq. (5)).     */
+typedef enum { FT_CORE_PER_EPOCH = 0, FT_CORE_PER_MINIBATCH = 1 } ft_core_step;
+
+typedef struct {
+    int64_t minibatch;         /* M >= 1: samples per minibatch Psi          */
+    double lr_A, lr_B;         /* gamma_A, gamma_B (finite, >= 0)            */
+    double lambda_A, lambda_B; /* lambda_A, lambda_B (finite, >= 0)          */
+    int32_t precision;         /* ft_precision                               */
+    int32_t row_scale;         /* ft_row_scale                               */
+    int32_t core_step;         /* ft_core_step                               */
+    int32_t deterministic;     /* 1: sorted segmented reductions, no float
+                                  atomics, bitwise reproducible;
+                                  0: Hogwild fast mode (per-sample updates
+                                  with atomics, no minibatch barrier)        */
+    uint64_t shuffle_seed;     /* seed of the device-side epoch order        */
+    int32_t reshuffle_each_epoch; /* 1: new order every epoch; 0: fixed     */
+} ft_options;
+
+/* Kernel classes that ft_profile_get reports. */
+typedef enum {
+    FT_K_ORDER = 0,        /* epoch order (counter-based permutation)        */
+    FT_K_PERMUTE = 1,      /* gather of the SoA streams into epoch order     */
+    FT_K_SORT = 2,         /* mode-sorted minibatch builder (all passes)     */
+    FT_K_FACTOR_GRAD = 3,  /* gather + contract + Hadamard + residual + grad */
+    FT_K_SEG_REDUCE = 4,   /* sorted segmented reduction + row update        */
+    FT_K_SEG_FIXUP = 5,    /* rows whose segment spans several chunks        */
+    FT_K_CORE_GRAD = 6,    /* core-gradient partials                         */
+    FT_K_CORE_UPDATE = 7,  /* fixed-order partial sum + core update          */
+    FT_K_EVAL = 8,         /* forward-only residual statistics               */
+    FT_K_HOGWILD = 9,      /* fast-mode factor sweep                         */
+    FT_K_COUNT = 10
+} ft_kernel;
+
+/* Fill *o with the defaults: M = 512, lr 0.01, lambda 1e-3, FP32, ROW_SUM,
+ * PER_EPOCH, deterministic, seed 0, reshuffle. */
+ft_status ft_default_options(ft_options *o);
+
+/* Create a problem of the given order with dims[order] = I_n, J[order] = J_n
+ * and Kruskal rank R (Section 2.3 problem statement). Factor and core
+ * matrices are initialised with N(0, 0.5^2) entries drawn from a SplitMix64
+ * stream seeded by seed (Algorithm 3's initialisation, which the paper leaves
+ * open). *out receives the handle; on failure *out is set to NULL and
+ * ft_last_error(NULL) names the reason. */
+ft_status ft_create(int order, const int64_t *dims, const int32_t *J,
+                    int32_t R, uint64_t seed, ft_handle **out);
+
+/* Release every resource of h (NULL is accepted). */
+ft_status ft_destroy(ft_handle *h);
+
+/* Message of the last failing call on h; h == NULL gives the last ft_create
+ * failure of the calling thread. Never NULL. */
+const char *ft_last_error(const ft_handle *h);
+
+ft_status ft_set_options(ft_handle *h, const ft_options *o);
+ft_status ft_get_options(const ft_handle *h, ft_options *o);
+
+/* Use a caller-provided HIP stream (hipStream_t, default priority) for all
+ * later work of h; NULL selects the null stream. */
+ft_status ft_set_stream(ft_handle *h, void *hip_stream);
+
+/* Copy a set of nonzeros (the set Omega, or the test set Gamma of Section
+ * 5.2). idx is structure-of-arrays: idx[n*nnz + s] is i_n of nonzero s;
+ * vals[s] its value. Every index is range-checked (FT_EINVAL, nothing
+ * changed). nnz may be 0 for the test set; the training set needs nnz >= 1.
+ * Replacing the training set resets the epoch order. */
+ft_status ft_set_nonzeros(ft_handle *h, ft_set which, int64_t nnz,
+                          const int32_t *idx, const float *vals);
+
+/* Visit the training set in the order perm[0..nnz_train) in every later
+ * epoch (a permutation of 0..nnz_train-1, checked); NULL returns to the
+ * device-side order drawn from shuffle_seed and the epoch counter. */
+ft_status ft_set_epoch_order(ft_handle *h, const int64_t *perm);
+
+/* Number of minibatches of one epoch: ceil(nnz_train / M). */
+ft_status ft_num_minibatches(const ft_handle *h, int64_t *out);
+
+/* One factor epoch (Algorithm 3 first loop): draw the order, build the
+ * mode-sorted minibatches, then for every minibatch compute c, d, the
+ * residual and the row gradients (Eq. (8)) with all parameters as they stand
+ * at the minibatch start, and update every touched row (Eq. (12), scaled by
+ * row_scale). mb_loss (NULL or [ceil(nnz/M)]) receives sum r^2/2 of every
+ * minibatch, r = xhat - x. Advances the epoch counter. */
+ft_status ft_epoch_factors(ft_handle *h, double *mb_loss);
+
+/* Fine-grained form of ft_epoch_factors for verification:
+ * ft_prepare_epoch draws the order and builds the minibatches;
+ * ft_factor_minibatch runs minibatch b of the prepared epoch. With apply = 1
+ * it updates A and writes sum r^2/2 to *loss (may be NULL). With apply = 0 it
+ * changes nothing and writes, for every mode n, the summed row gradients
+ * G^(n) (sum over occurrences of r*(B d) + lambda_A*a, dense I_n x J_n,
+ * row-major, zero for untouched rows) to grad[n] and the occurrence counts to
+ * count[n] (I_n entries). */
+ft_status ft_prepare_epoch(ft_handle *h);
+ft_status ft_factor_minibatch(ft_handle *h, int64_t b, int32_t apply,
+                              double *loss, float *const *grad,
+                              int32_t *const *count);
+
+/* One core epoch (Algorithm 5, or per-minibatch steps with
+ * FT_CORE_PER_MINIBATCH): Grad^(n) = sum_s r_s a^(n)T d^(n) with A, B fixed,
+ * then B^(n) <- B^(n) - lr_B (Grad^(n)/|Omega| + lambda_B B^(n)) for all n at
+ * once. *loss (may be NULL) receives sum r^2/2 over the training set. */
+ft_status ft_epoch_core(ft_handle *h, double *loss);
+
+/* Core gradient only: Grad^(n) (J_n x R row-major, no regulariser) summed
+ * over the training set into grad[n]; A and B unchanged. */
+ft_status ft_core_grad(ft_handle *h, float *const *grad, double *loss);
+
+/* Objective of Eq. (4) over a set, regularisers summed over all modes:
+ * sum (x - xhat)^2 + lambda_A sum_n ||A^(n)||^2 + lambda_B sum_n ||B^(n)||^2. */
+ft_status ft_loss(ft_handle *h, ft_set which, double *out);
+
+/* sqrt(mean (x - xhat)^2) over a set (test RMSE of Section 5.2); 0 for an
+ * empty set. ft_eval gives the raw sums: sum (x-xhat)^2 and sum |x-xhat|. */
+ft_status ft_rmse(ft_handle *h, ft_set which, double *out);
+ft_status ft_eval(ft_handle *h, ft_set which, double *sse, double *sae);
+
+/* Parameters, unpadded row-major: which = 0 gives A^(mode) (I_n x J_n),
+ * which = 1 gives B^(mode) (J_n x R). */
+ft_status ft_get_params(ft_handle *h, int mode, int which, float *host_out);
+ft_status ft_set_params(ft_handle *h, int mode, int which,
+                        const float *host_in);
+
+/* Builder output of the prepared epoch, for verification: the epoch order
+ * (nnz_train entries), and for minibatch b and mode n the in-minibatch
+ * positions sorted stably by row (pos[m]) and those rows (rows[m]),
+ * m = size of minibatch b. */
+ft_status ft_get_epoch_order(ft_handle *h, int64_t *perm_out);
+ft_status ft_get_minibatch_sort(ft_handle *h, int64_t b, int mode,
+                                int32_t *pos, int32_t *rows);
+
+/* Per-kernel device time: with profiling on, every launch is bracketed by HIP
+ * events on the handle's stream; ft_profile_get synchronises and returns the
+ * number of launches and their summed duration (ms) since the last reset. */
+ft_status ft_profile_enable(ft_handle *h, int32_t on);
+ft_status ft_profile_reset(ft_handle *h);
+ft_status ft_profile_get(ft_handle *h, int32_t kernel, int64_t *launches,
+                         double *total_ms);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FT_H */

@@ -1,0 +1,86 @@
+"""ctypes declarations of the C ABI in include/ft.h (argument marshalling only).
+
+The shared library is the in-tree libft.so; if it is missing the import of
+this package fails loudly -- there is no fallback path.
+"""
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libft.so")
+
+FT_OK, FT_EINVAL, FT_ENOMEM, FT_EDEVICE, FT_ESTATE, FT_ENONFINITE = range(6)
+STATUS_NAMES = {0: "FT_OK", 1: "FT_EINVAL", 2: "FT_ENOMEM", 3: "FT_EDEVICE",
+                4: "FT_ESTATE", 5: "FT_ENONFINITE"}
+FT_TRAIN, FT_TEST = 0, 1
+FT_FP32, FT_BF16, FT_FP8_E4M3 = 0, 1, 2
+FT_ROW_SUM, FT_ROW_MEAN = 0, 1
+FT_CORE_PER_EPOCH, FT_CORE_PER_MINIBATCH = 0, 1
+KERNELS = ["order", "permute", "sort", "factor_grad", "seg_reduce",
+           "seg_fixup", "core_grad", "core_update", "eval", "hogwild"]
+
+
+class Options(C.Structure):
+    _fields_ = [("minibatch", C.c_int64), ("lr_A", C.c_double),
+                ("lr_B", C.c_double), ("lambda_A", C.c_double),
+                ("lambda_B", C.c_double), ("precision", C.c_int32),
+                ("row_scale", C.c_int32), ("core_step", C.c_int32),
+                ("deterministic", C.c_int32), ("shuffle_seed", C.c_uint64),
+                ("reshuffle_each_epoch", C.c_int32)]
+
+
+_H = C.c_void_p
+_i32p = C.POINTER(C.c_int32)
+_i64p = C.POINTER(C.c_int64)
+_f32p = C.POINTER(C.c_float)
+_f64p = C.POINTER(C.c_double)
+
+# name -> (restype, argtypes)
+SIGNATURES = {
+    "ft_default_options": (C.c_int, [C.POINTER(Options)]),
+    "ft_create": (C.c_int, [C.c_int, _i64p, _i32p, C.c_int32, C.c_uint64,
+                            C.POINTER(_H)]),
+    "ft_destroy": (C.c_int, [_H]),
+    "ft_last_error": (C.c_char_p, [_H]),
+    "ft_set_options": (C.c_int, [_H, C.POINTER(Options)]),
+    "ft_get_options": (C.c_int, [_H, C.POINTER(Options)]),
+    "ft_set_stream": (C.c_int, [_H, C.c_void_p]),
+    "ft_set_nonzeros": (C.c_int, [_H, C.c_int, C.c_int64, _i32p, _f32p]),
+    "ft_set_epoch_order": (C.c_int, [_H, _i64p]),
+    "ft_num_minibatches": (C.c_int, [_H, _i64p]),
+    "ft_epoch_factors": (C.c_int, [_H, _f64p]),
+    "ft_prepare_epoch": (C.c_int, [_H]),
+    "ft_factor_minibatch": (C.c_int, [_H, C.c_int64, C.c_int32, _f64p,
+                                      C.POINTER(_f32p), C.POINTER(_i32p)]),
+    "ft_epoch_core": (C.c_int, [_H, _f64p]),
+    "ft_core_grad": (C.c_int, [_H, C.POINTER(_f32p), _f64p]),
+    "ft_loss": (C.c_int, [_H, C.c_int, _f64p]),
+    "ft_rmse": (C.c_int, [_H, C.c_int, _f64p]),
+    "ft_eval": (C.c_int, [_H, C.c_int, _f64p, _f64p]),
+    "ft_get_params": (C.c_int, [_H, C.c_int, C.c_int, _f32p]),
+    "ft_set_params": (C.c_int, [_H, C.c_int, C.c_int, _f32p]),
+    "ft_get_epoch_order": (C.c_int, [_H, _i64p]),
+    "ft_get_minibatch_sort": (C.c_int, [_H, C.c_int64, C.c_int, _i32p, _i32p]),
+    "ft_profile_enable": (C.c_int, [_H, C.c_int32]),
+    "ft_profile_reset": (C.c_int, [_H]),
+    "ft_profile_get": (C.c_int, [_H, C.c_int32, _i64p, _f64p]),
+}
+
+_lib = None
+
+
+def load():
+    """Load libft.so and declare every entry point; raises if it is absent."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"{LIB_PATH} is missing: build the HIP library first "
+                "(python -m paper_2404_10087_amd.build)")
+        lib = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib

@@ -1,0 +1,1032 @@
+// ft_api.cpp -- host runtime of the sparse FastTucker library: argument
+// validation, device memory, the epoch schedule and the C ABI of ft.h.
+//
+// Every entry point validates its arguments before touching the device, so
+// the boundary behaves the same on a host without a GPU (FT_EINVAL for bad
+// arguments, FT_EDEVICE when a valid call needs a device that is absent).
+#include "../../include/ft.h"
+#include "ft_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using namespace ft;
+
+namespace {
+thread_local std::string g_create_error = "no error";
+
+struct Pending {
+    int kind;
+    hipEvent_t a, b;
+};
+}  // namespace
+
+struct ft_handle {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int N = 0;
+    int64_t dims[kMaxOrder] = {};
+    int32_t J[kMaxOrder] = {};
+    int32_t R = 0;
+    Shape sh{};
+    ft_options opt{};
+    std::string err = "no error";
+
+    float *A[kMaxOrder] = {};
+    float *B[kMaxOrder] = {};
+
+    int64_t nnz[2] = {0, 0};
+    int32_t *idx[2][kMaxOrder] = {};
+    float *val[2] = {};
+
+    // epoch state
+    uint64_t epoch = 0;
+    bool use_user_perm = false;
+    uint32_t *user_perm = nullptr;
+    uint32_t *perm = nullptr;
+    int32_t *pidx[kMaxOrder] = {};
+    float *pval = nullptr;
+    uint32_t *sk[2][kMaxOrder] = {};
+    uint32_t *sv[2][kMaxOrder] = {};
+    uint32_t *counts = nullptr;
+    size_t counts_cap = 0;
+    int sort_final = 0;
+    bool prepared = false;
+    int64_t prepared_M = 0;
+
+    // factor-phase scratch
+    float *G = nullptr;
+    size_t G_cap = 0;
+    float *first = nullptr, *last = nullptr;
+    size_t fl_cap = 0;
+    double *mb_part = nullptr;
+    size_t mb_part_cap = 0;
+    double *mb_loss = nullptr;
+    size_t mb_loss_cap = 0;
+
+    // core-phase / evaluation scratch
+    float *core_part = nullptr;
+    size_t core_part_cap = 0;
+    double *dpart = nullptr;
+    size_t dpart_cap = 0;
+    double *scal = nullptr;   // 64 doubles
+
+    // profiling
+    bool prof = false;
+    std::vector<Pending> pending;
+    std::vector<hipEvent_t> pool;
+    int64_t launches[FT_K_COUNT] = {};
+    double ms[FT_K_COUNT] = {};
+};
+
+// ------------------------------------------------------------------ helpers
+static ft_status fail(ft_handle *h, ft_status code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (h) h->err = buf; else g_create_error = buf;
+    return code;
+}
+
+#define HIPCHK(h, expr)                                                      \
+    do {                                                                     \
+        hipError_t e_ = (expr);                                              \
+        if (e_ != hipSuccess)                                                \
+            return fail((h),                                                 \
+                        e_ == hipErrorOutOfMemory ? FT_ENOMEM : FT_EDEVICE,  \
+                        "%s failed: %s", #expr, hipGetErrorString(e_));      \
+    } while (0)
+
+#define CHECK_HANDLE(h)                                                      \
+    do {                                                                     \
+        if (!(h)) return fail(nullptr, FT_EINVAL, "handle is NULL");         \
+    } while (0)
+
+template <typename T>
+static hipError_t ensure(T **p, size_t *cap, size_t count) {
+    if (count <= *cap && *p) return hipSuccess;
+    if (*p) (void)hipFree(*p);
+    *p = nullptr;
+    *cap = 0;
+    hipError_t e = hipMalloc((void **)p, sizeof(T) * (count ? count : 1));
+    if (e == hipSuccess) *cap = count;
+    return e;
+}
+
+static void dfree(void *p) {
+    if (p) (void)hipFree(p);
+}
+
+static int64_t nminibatches(const ft_handle *h) {
+    return (h->nnz[FT_TRAIN] + h->opt.minibatch - 1) / h->opt.minibatch;
+}
+
+static void prof_begin(ft_handle *h, int kind) {
+    if (!h->prof) return;
+    hipEvent_t a;
+    if (h->pool.empty()) {
+        if (hipEventCreate(&a) != hipSuccess) return;
+    } else {
+        a = h->pool.back();
+        h->pool.pop_back();
+    }
+    (void)hipEventRecord(a, h->stream);
+    h->pending.push_back({kind, a, nullptr});
+}
+
+static void prof_end(ft_handle *h) {
+    if (!h->prof || h->pending.empty() || h->pending.back().b) return;
+    hipEvent_t b;
+    if (h->pool.empty()) {
+        if (hipEventCreate(&b) != hipSuccess) return;
+    } else {
+        b = h->pool.back();
+        h->pool.pop_back();
+    }
+    (void)hipEventRecord(b, h->stream);
+    h->pending.back().b = b;
+}
+
+static ft_status prof_collect(ft_handle *h) {
+    if (h->pending.empty()) return FT_OK;
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    for (auto &p : h->pending) {
+        if (p.b) {
+            float t = 0.f;
+            if (hipEventElapsedTime(&t, p.a, p.b) == hipSuccess) {
+                h->launches[p.kind] += 1;
+                h->ms[p.kind] += t;
+            }
+            h->pool.push_back(p.b);
+        }
+        h->pool.push_back(p.a);
+    }
+    h->pending.clear();
+    return FT_OK;
+}
+
+struct Launch {
+    ft_handle *h;
+    Launch(ft_handle *hh, int kind) : h(hh) { prof_begin(h, kind); }
+    ~Launch() { prof_end(h); }
+};
+
+// SplitMix64 (Steele, Lea & Flood, 2014) and the Box-Muller transform for the
+// seeded initial parameters.
+static uint64_t splitmix64(uint64_t &s) {
+    uint64_t z = (s += 0x9e3779b97f4a7c15ull);
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+static double normal01(uint64_t &s) {
+    const double u1 = 1.0 - (double)(splitmix64(s) >> 11) * 0x1.0p-53;
+    const double u2 = (double)(splitmix64(s) >> 11) * 0x1.0p-53;
+    return std::sqrt(-2.0 * std::log(u1)) * std::cos(6.283185307179586 * u2);
+}
+
+static ft_status upload_padded(ft_handle *h, float *dst, const float *src,
+                               int64_t rows, int cols, int ld) {
+    HIPCHK(h, hipMemcpy2DAsync(dst, sizeof(float) * ld, src,
+                               sizeof(float) * cols, sizeof(float) * cols, rows,
+                               hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    return FT_OK;
+}
+
+static ft_status download_padded(ft_handle *h, float *dst, const float *src,
+                                 int64_t rows, int cols, int ld) {
+    HIPCHK(h, hipMemcpy2DAsync(dst, sizeof(float) * cols, src,
+                               sizeof(float) * ld, sizeof(float) * cols, rows,
+                               hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    return FT_OK;
+}
+
+static void release(ft_handle *h) {
+    for (int n = 0; n < kMaxOrder; ++n) {
+        dfree(h->A[n]);
+        dfree(h->B[n]);
+        for (int s = 0; s < 2; ++s) {
+            dfree(h->idx[s][n]);
+            dfree(h->sk[s][n]);
+            dfree(h->sv[s][n]);
+        }
+        dfree(h->pidx[n]);
+    }
+    dfree(h->val[0]);
+    dfree(h->val[1]);
+    dfree(h->user_perm);
+    dfree(h->perm);
+    dfree(h->pval);
+    dfree(h->counts);
+    dfree(h->G);
+    dfree(h->first);
+    dfree(h->last);
+    dfree(h->mb_part);
+    dfree(h->mb_loss);
+    dfree(h->core_part);
+    dfree(h->dpart);
+    dfree(h->scal);
+    for (auto &p : h->pending) {
+        if (p.a) (void)hipEventDestroy(p.a);
+        if (p.b) (void)hipEventDestroy(p.b);
+    }
+    for (auto e : h->pool) (void)hipEventDestroy(e);
+}
+
+// ------------------------------------------------------------------ options
+extern "C" ft_status ft_default_options(ft_options *o) {
+    if (!o) return fail(nullptr, FT_EINVAL, "options pointer is NULL");
+    std::memset(o, 0, sizeof *o);
+    o->minibatch = 512;
+    o->lr_A = o->lr_B = 0.01;
+    o->lambda_A = o->lambda_B = 1e-3;
+    o->precision = FT_FP32;
+    o->row_scale = FT_ROW_SUM;
+    o->core_step = FT_CORE_PER_EPOCH;
+    o->deterministic = 1;
+    o->shuffle_seed = 0;
+    o->reshuffle_each_epoch = 1;
+    return FT_OK;
+}
+
+extern "C" const char *ft_last_error(const ft_handle *h) {
+    return h ? h->err.c_str() : g_create_error.c_str();
+}
+
+static ft_status check_options(ft_handle *h, const ft_options *o) {
+    if (!o) return fail(h, FT_EINVAL, "options pointer is NULL");
+    if (o->minibatch < 1 || o->minibatch > (1ll << 30))
+        return fail(h, FT_EINVAL, "minibatch must be in [1, 2^30], got %lld",
+                    (long long)o->minibatch);
+    const double v[4] = {o->lr_A, o->lr_B, o->lambda_A, o->lambda_B};
+    for (double x : v)
+        if (!std::isfinite(x) || x < 0)
+            return fail(h, FT_EINVAL,
+                        "learning rates and lambdas must be finite and >= 0");
+    if (o->precision != FT_FP32)
+        return fail(h, FT_EINVAL,
+                    "precision %d is not available in this build (FP32 only)",
+                    o->precision);
+    if (o->row_scale != FT_ROW_SUM && o->row_scale != FT_ROW_MEAN)
+        return fail(h, FT_EINVAL, "row_scale must be FT_ROW_SUM or FT_ROW_MEAN");
+    if (o->core_step != FT_CORE_PER_EPOCH &&
+        o->core_step != FT_CORE_PER_MINIBATCH)
+        return fail(h, FT_EINVAL, "core_step must be PER_EPOCH or PER_MINIBATCH");
+    if (o->deterministic != 1)
+        return fail(h, FT_EINVAL,
+                    "the Hogwild fast mode is not available in this build");
+    if (o->reshuffle_each_epoch != 0 && o->reshuffle_each_epoch != 1)
+        return fail(h, FT_EINVAL, "reshuffle_each_epoch must be 0 or 1");
+    return FT_OK;
+}
+
+extern "C" ft_status ft_set_options(ft_handle *h, const ft_options *o) {
+    CHECK_HANDLE(h);
+    ft_status st = check_options(h, o);
+    if (st != FT_OK) return st;
+    if (o->minibatch != h->opt.minibatch ||
+        o->shuffle_seed != h->opt.shuffle_seed ||
+        o->reshuffle_each_epoch != h->opt.reshuffle_each_epoch)
+        h->prepared = false;
+    h->opt = *o;
+    return FT_OK;
+}
+
+extern "C" ft_status ft_get_options(const ft_handle *h, ft_options *o) {
+    if (!h) return fail(nullptr, FT_EINVAL, "handle is NULL");
+    if (!o) return FT_EINVAL;
+    *o = h->opt;
+    return FT_OK;
+}
+
+extern "C" ft_status ft_set_stream(ft_handle *h, void *hip_stream) {
+    CHECK_HANDLE(h);
+    h->stream = (hipStream_t)hip_stream;
+    return FT_OK;
+}
+
+// ------------------------------------------------------------------ create
+extern "C" ft_status ft_create(int order, const int64_t *dims,
+                               const int32_t *J, int32_t R, uint64_t seed,
+                               ft_handle **out) {
+    if (!out) return fail(nullptr, FT_EINVAL, "out pointer is NULL");
+    *out = nullptr;
+    if (order < 2 || order > kMaxOrder)
+        return fail(nullptr, FT_EINVAL,
+                    "order must be in [2, %d] on the device path, got %d",
+                    kMaxOrder, order);
+    if (!dims || !J) return fail(nullptr, FT_EINVAL, "dims or J is NULL");
+    for (int n = 0; n < order; ++n) {
+        if (dims[n] < 1 || dims[n] > 0x7fffffffll)
+            return fail(nullptr, FT_EINVAL, "dims[%d] = %lld out of [1, 2^31)",
+                        n, (long long)dims[n]);
+        if (J[n] < 1 || J[n] > kMaxJ)
+            return fail(nullptr, FT_EINVAL, "J[%d] = %d out of [1, %d]", n,
+                        J[n], kMaxJ);
+    }
+    if (R < 1 || R > kMaxR)
+        return fail(nullptr, FT_EINVAL, "R = %d out of [1, %d]", R, kMaxR);
+
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1)
+        return fail(nullptr, FT_EDEVICE, "no HIP device is available");
+
+    ft_handle *h = new (std::nothrow) ft_handle();
+    if (!h) return fail(nullptr, FT_ENOMEM, "out of host memory");
+    if (hipGetDevice(&h->device) != hipSuccess) {
+        delete h;
+        return fail(nullptr, FT_EDEVICE, "hipGetDevice failed");
+    }
+    h->N = order;
+    int jmax = 0;
+    for (int n = 0; n < order; ++n) {
+        h->dims[n] = dims[n];
+        h->J[n] = J[n];
+        if (J[n] > jmax) jmax = J[n];
+    }
+    h->R = R;
+    h->sh.N = order;
+    h->sh.J4 = (jmax + 3) / 4 * 4;
+    h->sh.R16 = (R + 15) / 16 * 16;
+    ft_default_options(&h->opt);
+
+    ft_status st = FT_OK;
+    std::vector<float> hostbuf;
+    uint64_t rng = seed;
+    for (int n = 0; n < order && st == FT_OK; ++n) {
+        size_t capA = 0, capB = 0;
+        hipError_t e = ensure(&h->A[n], &capA, (size_t)dims[n] * h->sh.J4);
+        if (e == hipSuccess)
+            e = ensure(&h->B[n], &capB, (size_t)h->sh.J4 * h->sh.R16);
+        if (e == hipSuccess)
+            e = hipMemset(h->A[n], 0, sizeof(float) * dims[n] * h->sh.J4);
+        if (e == hipSuccess)
+            e = hipMemset(h->B[n], 0, sizeof(float) * h->sh.J4 * h->sh.R16);
+        if (e != hipSuccess) {
+            st = fail(nullptr, e == hipErrorOutOfMemory ? FT_ENOMEM : FT_EDEVICE,
+                      "allocation of parameters failed: %s",
+                      hipGetErrorString(e));
+            break;
+        }
+        hostbuf.assign((size_t)dims[n] * J[n], 0.f);
+        for (auto &x : hostbuf) x = (float)(0.5 * normal01(rng));
+        st = upload_padded(h, h->A[n], hostbuf.data(), dims[n], J[n], h->sh.J4);
+        if (st != FT_OK) break;
+        hostbuf.assign((size_t)J[n] * R, 0.f);
+        for (auto &x : hostbuf) x = (float)(0.5 * normal01(rng));
+        st = upload_padded(h, h->B[n], hostbuf.data(), J[n], R, h->sh.R16);
+    }
+    if (st == FT_OK) {
+        size_t cap = 0;
+        hipError_t e = ensure(&h->scal, &cap, 64);
+        if (e != hipSuccess)
+            st = fail(nullptr, FT_ENOMEM, "allocation failed: %s",
+                      hipGetErrorString(e));
+    }
+    if (st != FT_OK) {
+        if (h->err != "no error") g_create_error = h->err;
+        release(h);
+        delete h;
+        return st;
+    }
+    *out = h;
+    return FT_OK;
+}
+
+extern "C" ft_status ft_destroy(ft_handle *h) {
+    if (!h) return FT_OK;
+    (void)hipStreamSynchronize(h->stream);
+    release(h);
+    delete h;
+    return FT_OK;
+}
+
+// ------------------------------------------------------------------ data
+extern "C" ft_status ft_set_nonzeros(ft_handle *h, ft_set which, int64_t nnz,
+                                     const int32_t *idx, const float *vals) {
+    CHECK_HANDLE(h);
+    if (which != FT_TRAIN && which != FT_TEST)
+        return fail(h, FT_EINVAL, "which must be FT_TRAIN or FT_TEST");
+    if (nnz < 0 || nnz > 0x7fffffffll)
+        return fail(h, FT_EINVAL, "nnz = %lld out of [0, 2^31)", (long long)nnz);
+    if (which == FT_TRAIN && nnz < 1)
+        return fail(h, FT_EINVAL, "the training set needs at least 1 nonzero");
+    if (nnz > 0 && (!idx || !vals))
+        return fail(h, FT_EINVAL, "idx or vals is NULL");
+    for (int n = 0; n < h->N; ++n) {
+        const int32_t *row = idx + (size_t)n * nnz;
+        const int64_t I = h->dims[n];
+        for (int64_t s = 0; s < nnz; ++s)
+            if (row[s] < 0 || row[s] >= I)
+                return fail(h, FT_EINVAL,
+                            "index %d of nonzero %lld in mode %d is out of "
+                            "[0, %lld)",
+                            row[s], (long long)s, n, (long long)I);
+    }
+    for (int64_t s = 0; s < nnz; ++s)
+        if (!std::isfinite(vals[s]))
+            return fail(h, FT_EINVAL, "value of nonzero %lld is not finite",
+                        (long long)s);
+
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    for (int n = 0; n < h->N; ++n) {
+        dfree(h->idx[which][n]);
+        h->idx[which][n] = nullptr;
+    }
+    dfree(h->val[which]);
+    h->val[which] = nullptr;
+    h->nnz[which] = 0;
+    if (nnz > 0) {
+        for (int n = 0; n < h->N; ++n) {
+            HIPCHK(h, hipMalloc(&h->idx[which][n], sizeof(int32_t) * nnz));
+            HIPCHK(h, hipMemcpy(h->idx[which][n], idx + (size_t)n * nnz,
+                                sizeof(int32_t) * nnz, hipMemcpyHostToDevice));
+        }
+        HIPCHK(h, hipMalloc(&h->val[which], sizeof(float) * nnz));
+        HIPCHK(h, hipMemcpy(h->val[which], vals, sizeof(float) * nnz,
+                            hipMemcpyHostToDevice));
+    }
+    h->nnz[which] = nnz;
+    if (which == FT_TRAIN) {
+        h->use_user_perm = false;
+        h->prepared = false;
+        h->epoch = 0;
+        dfree(h->user_perm);
+        h->user_perm = nullptr;
+        dfree(h->perm);
+        h->perm = nullptr;
+        dfree(h->pval);
+        h->pval = nullptr;
+        HIPCHK(h, hipMalloc(&h->perm, sizeof(uint32_t) * nnz));
+        HIPCHK(h, hipMalloc(&h->pval, sizeof(float) * nnz));
+        for (int n = 0; n < h->N; ++n) {
+            dfree(h->pidx[n]);
+            h->pidx[n] = nullptr;
+            HIPCHK(h, hipMalloc(&h->pidx[n], sizeof(int32_t) * nnz));
+            for (int s = 0; s < 2; ++s) {
+                dfree(h->sk[s][n]);
+                dfree(h->sv[s][n]);
+                h->sk[s][n] = h->sv[s][n] = nullptr;
+                HIPCHK(h, hipMalloc(&h->sk[s][n], sizeof(uint32_t) * nnz));
+                HIPCHK(h, hipMalloc(&h->sv[s][n], sizeof(uint32_t) * nnz));
+            }
+        }
+    }
+    return FT_OK;
+}
+
+extern "C" ft_status ft_set_epoch_order(ft_handle *h, const int64_t *perm) {
+    CHECK_HANDLE(h);
+    const int64_t nnz = h->nnz[FT_TRAIN];
+    if (nnz < 1) return fail(h, FT_ESTATE, "no training set");
+    if (!perm) {
+        h->use_user_perm = false;
+        h->prepared = false;
+        return FT_OK;
+    }
+    std::vector<uint8_t> seen((size_t)nnz, 0);
+    std::vector<uint32_t> p32((size_t)nnz);
+    for (int64_t i = 0; i < nnz; ++i) {
+        const int64_t v = perm[i];
+        if (v < 0 || v >= nnz || seen[(size_t)v])
+            return fail(h, FT_EINVAL,
+                        "perm is not a permutation of [0, %lld) (entry %lld)",
+                        (long long)nnz, (long long)i);
+        seen[(size_t)v] = 1;
+        p32[(size_t)i] = (uint32_t)v;
+    }
+    if (!h->user_perm) HIPCHK(h, hipMalloc(&h->user_perm, sizeof(uint32_t) * nnz));
+    HIPCHK(h, hipMemcpy(h->user_perm, p32.data(), sizeof(uint32_t) * nnz,
+                        hipMemcpyHostToDevice));
+    h->use_user_perm = true;
+    h->prepared = false;
+    return FT_OK;
+}
+
+extern "C" ft_status ft_num_minibatches(const ft_handle *h, int64_t *out) {
+    if (!h) return fail(nullptr, FT_EINVAL, "handle is NULL");
+    if (!out) return FT_EINVAL;
+    *out = h->nnz[FT_TRAIN] > 0 ? nminibatches(h) : 0;
+    return FT_OK;
+}
+
+// ------------------------------------------------------------------ builder
+static ft_status draw_order(ft_handle *h, uint64_t salt) {
+    const int64_t nnz = h->nnz[FT_TRAIN];
+    Launch L(h, FT_K_ORDER);
+    if (h->use_user_perm) {
+        HIPCHK(h, hipMemcpyAsync(h->perm, h->user_perm, sizeof(uint32_t) * nnz,
+                                 hipMemcpyDeviceToDevice, h->stream));
+    } else {
+        const uint64_t e = h->opt.reshuffle_each_epoch ? h->epoch : 0;
+        const uint64_t key = h->opt.shuffle_seed ^
+                             (0x9e3779b97f4a7c15ull * (2 * e + 1 + 2 * salt));
+        HIPCHK(h, launch_epoch_order(h->perm, nnz, key, h->stream));
+    }
+    return FT_OK;
+}
+
+static ft_status permute_streams(ft_handle *h) {
+    Launch L(h, FT_K_PERMUTE);
+    HIPCHK(h, launch_permute(h->N, h->idx[FT_TRAIN], h->val[FT_TRAIN], h->perm,
+                             h->nnz[FT_TRAIN], h->pidx, h->pval, h->stream));
+    return FT_OK;
+}
+
+static ft_status build_minibatches(ft_handle *h) {
+    const int64_t nnz = h->nnz[FT_TRAIN];
+    const int64_t M = h->opt.minibatch;
+    const int nseg = (int)nminibatches(h);
+    const int tps = (int)((std::min<int64_t>(M, nnz) + kSortTile - 1) / kSortTile);
+    int64_t maxrow = 0;
+    for (int n = 0; n < h->N; ++n)
+        if (h->dims[n] - 1 > maxrow) maxrow = h->dims[n] - 1;
+    int bits = 0;
+    while ((1ll << bits) <= maxrow) ++bits;
+    const int passes = bits == 0 ? 1 : (bits + 7) / 8;
+    HIPCHK(h, ensure(&h->counts, &h->counts_cap,
+                     (size_t)h->N * nseg * kRadix * tps));
+    Launch L(h, FT_K_SORT);
+    SortPass p{};
+    p.N = h->N;
+    p.nnz = nnz;
+    p.M = M;
+    p.nseg = nseg;
+    p.tiles_per_seg = tps;
+    p.counts = h->counts;
+    int cur = 0;
+    for (int pass = 0; pass < passes; ++pass) {
+        p.shift = 8 * pass;
+        for (int n = 0; n < h->N; ++n) {
+            p.key_in[n] = pass == 0 ? reinterpret_cast<const uint32_t *>(h->pidx[n])
+                                    : h->sk[cur][n];
+            p.val_in[n] = pass == 0 ? nullptr : h->sv[cur][n];
+            p.key_out[n] = h->sk[pass == 0 ? 0 : cur ^ 1][n];
+            p.val_out[n] = h->sv[pass == 0 ? 0 : cur ^ 1][n];
+        }
+        cur = pass == 0 ? 0 : cur ^ 1;
+        HIPCHK(h, launch_sort_pass(p, h->stream));
+    }
+    h->sort_final = cur;
+    return FT_OK;
+}
+
+static ft_status prepare(ft_handle *h) {
+    if (h->nnz[FT_TRAIN] < 1) return fail(h, FT_ESTATE, "no training set");
+    ft_status st = draw_order(h, 0);
+    if (st == FT_OK) st = permute_streams(h);
+    if (st == FT_OK) st = build_minibatches(h);
+    if (st != FT_OK) return st;
+    h->prepared = true;
+    h->prepared_M = h->opt.minibatch;
+    return FT_OK;
+}
+
+extern "C" ft_status ft_prepare_epoch(ft_handle *h) {
+    CHECK_HANDLE(h);
+    return prepare(h);
+}
+
+// ------------------------------------------------------------------ factor
+static ft_status run_minibatch(ft_handle *h, int64_t b, int apply,
+                               double *loss_part, float *const *grad,
+                               int32_t *const *count) {
+    const int64_t M = h->opt.minibatch;
+    const int64_t off = b * M;
+    const int32_t m = (int32_t)std::min<int64_t>(M, h->nnz[FT_TRAIN] - off);
+    FactorArgs fa{};
+    for (int n = 0; n < h->N; ++n) {
+        fa.idx[n] = h->pidx[n] + off;
+        fa.A[n] = h->A[n];
+        fa.B[n] = h->B[n];
+    }
+    fa.val = h->pval + off;
+    fa.m = m;
+    fa.G = h->G;
+    fa.loss_part = loss_part;
+    int nb = 0;
+    {
+        Launch L(h, FT_K_FACTOR_GRAD);
+        HIPCHK(h, launch_factor_grad(h->sh, fa, &nb, h->stream));
+    }
+    SegArgs sa{};
+    sa.N = h->N;
+    sa.J4 = h->sh.J4;
+    sa.m = m;
+    sa.nchunks = (m + kSegChunk - 1) / kSegChunk;
+    for (int n = 0; n < h->N; ++n) {
+        sa.rows[n] = h->sk[h->sort_final][n] + off;
+        sa.pos[n] = h->sv[h->sort_final][n] + off;
+        sa.A[n] = h->A[n];
+        sa.grad[n] = grad ? grad[n] : nullptr;
+        sa.count[n] = count ? count[n] : nullptr;
+    }
+    sa.G = h->G;
+    sa.first = h->first;
+    sa.last = h->last;
+    sa.lr = (float)h->opt.lr_A;
+    sa.lam = (float)h->opt.lambda_A;
+    sa.mean = h->opt.row_scale == FT_ROW_MEAN;
+    sa.apply = apply;
+    {
+        Launch L(h, FT_K_SEG_REDUCE);
+        HIPCHK(h, launch_seg_reduce(sa, h->stream));
+    }
+    {
+        Launch L(h, FT_K_SEG_FIXUP);
+        HIPCHK(h, launch_seg_fixup(sa, h->stream));
+    }
+    return FT_OK;
+}
+
+static ft_status alloc_factor(ft_handle *h, int64_t nmb, int nper) {
+    const int64_t M = std::min<int64_t>(h->opt.minibatch, h->nnz[FT_TRAIN]);
+    const int64_t nch = (M + kSegChunk - 1) / kSegChunk;
+    HIPCHK(h, ensure(&h->G, &h->G_cap, (size_t)h->N * M * h->sh.J4));
+    size_t cap_first = h->fl_cap, cap_last = h->fl_cap;
+    HIPCHK(h, ensure(&h->first, &cap_first, (size_t)h->N * nch * h->sh.J4));
+    HIPCHK(h, ensure(&h->last, &cap_last, (size_t)h->N * nch * h->sh.J4));
+    h->fl_cap = std::min(cap_first, cap_last);
+    HIPCHK(h, ensure(&h->mb_part, &h->mb_part_cap, (size_t)nmb * nper));
+    HIPCHK(h, ensure(&h->mb_loss, &h->mb_loss_cap, (size_t)nmb));
+    return FT_OK;
+}
+
+extern "C" ft_status ft_epoch_factors(ft_handle *h, double *mb_loss) {
+    CHECK_HANDLE(h);
+    if (h->nnz[FT_TRAIN] < 1) return fail(h, FT_ESTATE, "no training set");
+    const bool reuse = h->prepared && !h->opt.reshuffle_each_epoch &&
+                       h->prepared_M == h->opt.minibatch;
+    if (!reuse) {
+        ft_status st = prepare(h);
+        if (st != FT_OK) return st;
+    }
+    const int64_t nmb = nminibatches(h);
+    const int nper = factor_grad_blocks(
+        (int32_t)std::min<int64_t>(h->opt.minibatch, h->nnz[FT_TRAIN]));
+    ft_status st = alloc_factor(h, nmb, nper);
+    if (st != FT_OK) return st;
+    HIPCHK(h, hipMemsetAsync(h->mb_part, 0, sizeof(double) * nmb * nper,
+                             h->stream));
+    for (int64_t b = 0; b < nmb; ++b) {
+        st = run_minibatch(h, b, 1, h->mb_part + b * nper, nullptr, nullptr);
+        if (st != FT_OK) return st;
+    }
+    HIPCHK(h, launch_sum_blocks(h->mb_part, nper, (int)nmb, h->mb_loss,
+                                h->stream));
+    std::vector<double> losses((size_t)nmb);
+    HIPCHK(h, hipMemcpyAsync(losses.data(), h->mb_loss, sizeof(double) * nmb,
+                             hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    h->epoch += 1;
+    if (mb_loss) std::memcpy(mb_loss, losses.data(), sizeof(double) * nmb);
+    for (double l : losses)
+        if (!std::isfinite(l))
+            return fail(h, FT_ENONFINITE, "a minibatch loss is not finite");
+    return FT_OK;
+}
+
+extern "C" ft_status ft_factor_minibatch(ft_handle *h, int64_t b,
+                                         int32_t apply, double *loss,
+                                         float *const *grad,
+                                         int32_t *const *count) {
+    CHECK_HANDLE(h);
+    if (!h->prepared || h->prepared_M != h->opt.minibatch)
+        return fail(h, FT_ESTATE, "no prepared epoch (call ft_prepare_epoch)");
+    const int64_t nmb = nminibatches(h);
+    if (b < 0 || b >= nmb)
+        return fail(h, FT_EINVAL, "minibatch %lld out of [0, %lld)",
+                    (long long)b, (long long)nmb);
+    if (apply != 0 && apply != 1)
+        return fail(h, FT_EINVAL, "apply must be 0 or 1");
+    if (!apply && (!grad || !count))
+        return fail(h, FT_EINVAL, "apply = 0 needs grad and count buffers");
+    if (!apply)
+        for (int n = 0; n < h->N; ++n)
+            if (!grad[n] || !count[n])
+                return fail(h, FT_EINVAL, "grad[%d] or count[%d] is NULL", n, n);
+    const int nper = factor_grad_blocks(
+        (int32_t)std::min<int64_t>(h->opt.minibatch, h->nnz[FT_TRAIN]));
+    ft_status st = alloc_factor(h, nmb, nper);
+    if (st != FT_OK) return st;
+    float *dgrad[kMaxOrder] = {};
+    int32_t *dcount[kMaxOrder] = {};
+    struct Guard {
+        float **g;
+        int32_t **c;
+        ~Guard() {
+            for (int n = 0; n < kMaxOrder; ++n) {
+                dfree(g[n]);
+                dfree(c[n]);
+            }
+        }
+    } guard{dgrad, dcount};
+    if (!apply) {
+        for (int n = 0; n < h->N; ++n) {
+            HIPCHK(h, hipMalloc(&dgrad[n], sizeof(float) * h->dims[n] * h->sh.J4));
+            HIPCHK(h, hipMalloc(&dcount[n], sizeof(int32_t) * h->dims[n]));
+            HIPCHK(h, hipMemsetAsync(dgrad[n], 0,
+                                     sizeof(float) * h->dims[n] * h->sh.J4,
+                                     h->stream));
+            HIPCHK(h, hipMemsetAsync(dcount[n], 0, sizeof(int32_t) * h->dims[n],
+                                     h->stream));
+        }
+    }
+    HIPCHK(h, hipMemsetAsync(h->mb_part, 0, sizeof(double) * nper, h->stream));
+    st = run_minibatch(h, b, apply, h->mb_part, apply ? nullptr : dgrad,
+                       apply ? nullptr : dcount);
+    if (st != FT_OK) return st;
+    HIPCHK(h, launch_sum_blocks(h->mb_part, nper, 1, h->scal, h->stream));
+    double l = 0.0;
+    HIPCHK(h, hipMemcpyAsync(&l, h->scal, sizeof(double), hipMemcpyDeviceToHost,
+                             h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    if (loss) *loss = l;
+    if (!apply) {
+        for (int n = 0; n < h->N; ++n) {
+            st = download_padded(h, grad[n], dgrad[n], h->dims[n], h->J[n],
+                                 h->sh.J4);
+            if (st != FT_OK) return st;
+            HIPCHK(h, hipMemcpy(count[n], dcount[n],
+                                sizeof(int32_t) * h->dims[n],
+                                hipMemcpyDeviceToHost));
+        }
+    }
+    return FT_OK;
+}
+
+// ------------------------------------------------------------------ core
+static ft_status core_pass(ft_handle *h, const int32_t *const *idx,
+                           const float *val, int64_t count, int apply,
+                           float *grad_out, double *loss_dev) {
+    const int nb = core_grad_blocks(count);
+    const size_t E = (size_t)h->N * h->sh.J4 * h->sh.R16;
+    HIPCHK(h, ensure(&h->core_part, &h->core_part_cap, (size_t)nb * E));
+    HIPCHK(h, ensure(&h->dpart, &h->dpart_cap, (size_t)2 * kMaxOrder * 1024 + 4096));
+    CoreArgs ca{};
+    for (int n = 0; n < h->N; ++n) {
+        ca.idx[n] = idx[n];
+        ca.A[n] = h->A[n];
+        ca.B[n] = h->B[n];
+    }
+    ca.val = val;
+    ca.count = count;
+    ca.part = h->core_part;
+    ca.loss_part = h->dpart;
+    {
+        Launch L(h, FT_K_CORE_GRAD);
+        HIPCHK(h, launch_core_grad(h->sh, ca, nb, h->stream));
+    }
+    CoreUpdateArgs ua{};
+    ua.part = h->core_part;
+    ua.nblocks = nb;
+    for (int n = 0; n < h->N; ++n) ua.B[n] = h->B[n];
+    ua.grad_out = grad_out;
+    ua.inv_count = 1.0 / (double)count;
+    ua.lr = (float)h->opt.lr_B;
+    ua.lam = (float)h->opt.lambda_B;
+    ua.apply = apply;
+    {
+        Launch L(h, FT_K_CORE_UPDATE);
+        HIPCHK(h, launch_core_update(h->sh, ua, h->stream));
+    }
+    HIPCHK(h, launch_sum_blocks(h->dpart, nb, 1, loss_dev, h->stream));
+    return FT_OK;
+}
+
+extern "C" ft_status ft_epoch_core(ft_handle *h, double *loss) {
+    CHECK_HANDLE(h);
+    const int64_t nnz = h->nnz[FT_TRAIN];
+    if (nnz < 1) return fail(h, FT_ESTATE, "no training set");
+    double l = 0.0;
+    if (h->opt.core_step == FT_CORE_PER_EPOCH) {
+        ft_status st = core_pass(h, h->idx[FT_TRAIN], h->val[FT_TRAIN], nnz, 1,
+                                 nullptr, h->scal);
+        if (st != FT_OK) return st;
+        HIPCHK(h, hipMemcpyAsync(&l, h->scal, sizeof(double),
+                                 hipMemcpyDeviceToHost, h->stream));
+    } else {
+        ft_status st = draw_order(h, 1);
+        if (st == FT_OK) st = permute_streams(h);
+        if (st != FT_OK) return st;
+        h->prepared = false;   // the permuted streams now hold this order
+        const int64_t M = h->opt.minibatch;
+        const int64_t nmb = nminibatches(h);
+        HIPCHK(h, ensure(&h->mb_loss, &h->mb_loss_cap, (size_t)nmb));
+        for (int64_t b = 0; b < nmb; ++b) {
+            const int64_t off = b * M;
+            const int64_t m = std::min<int64_t>(M, nnz - off);
+            const int32_t *pi[kMaxOrder] = {};
+            for (int n = 0; n < h->N; ++n) pi[n] = h->pidx[n] + off;
+            st = core_pass(h, pi, h->pval + off, m, 1, nullptr, h->mb_loss + b);
+            if (st != FT_OK) return st;
+        }
+        HIPCHK(h, launch_sum_blocks(h->mb_loss, (int)nmb, 1, h->scal, h->stream));
+        HIPCHK(h, hipMemcpyAsync(&l, h->scal, sizeof(double),
+                                 hipMemcpyDeviceToHost, h->stream));
+    }
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    if (loss) *loss = l;
+    if (!std::isfinite(l))
+        return fail(h, FT_ENONFINITE, "the core-phase loss is not finite");
+    return FT_OK;
+}
+
+extern "C" ft_status ft_core_grad(ft_handle *h, float *const *grad,
+                                  double *loss) {
+    CHECK_HANDLE(h);
+    if (!grad) return fail(h, FT_EINVAL, "grad is NULL");
+    for (int n = 0; n < h->N; ++n)
+        if (!grad[n]) return fail(h, FT_EINVAL, "grad[%d] is NULL", n);
+    const int64_t nnz = h->nnz[FT_TRAIN];
+    if (nnz < 1) return fail(h, FT_ESTATE, "no training set");
+    const size_t E = (size_t)h->N * h->sh.J4 * h->sh.R16;
+    float *dg = nullptr;
+    HIPCHK(h, hipMalloc(&dg, sizeof(float) * E));
+    ft_status st = core_pass(h, h->idx[FT_TRAIN], h->val[FT_TRAIN], nnz, 0, dg,
+                             h->scal);
+    double l = 0.0;
+    if (st == FT_OK) {
+        hipError_t e = hipMemcpyAsync(&l, h->scal, sizeof(double),
+                                      hipMemcpyDeviceToHost, h->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+        if (e != hipSuccess) st = fail(h, FT_EDEVICE, "copy failed");
+    }
+    for (int n = 0; n < h->N && st == FT_OK; ++n)
+        st = download_padded(h, grad[n], dg + (size_t)n * h->sh.J4 * h->sh.R16,
+                             h->J[n], h->R, h->sh.R16);
+    dfree(dg);
+    if (st == FT_OK && loss) *loss = l;
+    return st;
+}
+
+// ------------------------------------------------------------------ evaluation
+extern "C" ft_status ft_eval(ft_handle *h, ft_set which, double *sse,
+                             double *sae) {
+    CHECK_HANDLE(h);
+    if (which != FT_TRAIN && which != FT_TEST)
+        return fail(h, FT_EINVAL, "which must be FT_TRAIN or FT_TEST");
+    const int64_t count = h->nnz[which];
+    double out[2] = {0.0, 0.0};
+    if (count > 0) {
+        const int nb = eval_blocks(count);
+        HIPCHK(h, ensure(&h->dpart, &h->dpart_cap, (size_t)2 * kMaxOrder * 1024 + 4096));
+        EvalArgs ea{};
+        for (int n = 0; n < h->N; ++n) {
+            ea.idx[n] = h->idx[which][n];
+            ea.A[n] = h->A[n];
+            ea.B[n] = h->B[n];
+        }
+        ea.val = h->val[which];
+        ea.count = count;
+        ea.part = h->dpart;
+        {
+            Launch L(h, FT_K_EVAL);
+            HIPCHK(h, launch_eval(h->sh, ea, nb, h->stream));
+        }
+        HIPCHK(h, launch_sum_blocks(h->dpart, nb, 2, h->scal, h->stream));
+        HIPCHK(h, hipMemcpyAsync(out, h->scal, sizeof out, hipMemcpyDeviceToHost,
+                                 h->stream));
+        HIPCHK(h, hipStreamSynchronize(h->stream));
+    }
+    if (sse) *sse = out[0];
+    if (sae) *sae = out[1];
+    return FT_OK;
+}
+
+extern "C" ft_status ft_rmse(ft_handle *h, ft_set which, double *out) {
+    CHECK_HANDLE(h);
+    if (!out) return fail(h, FT_EINVAL, "out is NULL");
+    double sse = 0.0;
+    ft_status st = ft_eval(h, which, &sse, nullptr);
+    if (st != FT_OK) return st;
+    const int64_t count = h->nnz[which];
+    *out = count > 0 ? std::sqrt(sse / (double)count) : 0.0;
+    return FT_OK;
+}
+
+extern "C" ft_status ft_loss(ft_handle *h, ft_set which, double *out) {
+    CHECK_HANDLE(h);
+    if (!out) return fail(h, FT_EINVAL, "out is NULL");
+    double sse = 0.0;
+    ft_status st = ft_eval(h, which, &sse, nullptr);
+    if (st != FT_OK) return st;
+    const int nb = 256;
+    HIPCHK(h, ensure(&h->dpart, &h->dpart_cap, (size_t)2 * kMaxOrder * 1024 + 4096));
+    for (int n = 0; n < h->N; ++n) {
+        HIPCHK(h, launch_sumsq(h->A[n], h->dims[n] * h->sh.J4,
+                               h->dpart + (size_t)(2 * n) * nb, nb, h->stream));
+        HIPCHK(h, launch_sumsq(h->B[n], (int64_t)h->sh.J4 * h->sh.R16,
+                               h->dpart + (size_t)(2 * n + 1) * nb, nb,
+                               h->stream));
+    }
+    HIPCHK(h, launch_sum_blocks(h->dpart, nb, 2 * h->N, h->scal, h->stream));
+    double norms[2 * kMaxOrder] = {};
+    HIPCHK(h, hipMemcpyAsync(norms, h->scal, sizeof(double) * 2 * h->N,
+                             hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    double na = 0.0, nbsum = 0.0;
+    for (int n = 0; n < h->N; ++n) {
+        na += norms[2 * n];
+        nbsum += norms[2 * n + 1];
+    }
+    *out = sse + h->opt.lambda_A * na + h->opt.lambda_B * nbsum;
+    return FT_OK;
+}
+
+// ------------------------------------------------------------------ params
+extern "C" ft_status ft_get_params(ft_handle *h, int mode, int which,
+                                   float *host_out) {
+    CHECK_HANDLE(h);
+    if (mode < 0 || mode >= h->N || (which != 0 && which != 1) || !host_out)
+        return fail(h, FT_EINVAL, "bad mode/which/out");
+    if (which == 0)
+        return download_padded(h, host_out, h->A[mode], h->dims[mode],
+                               h->J[mode], h->sh.J4);
+    return download_padded(h, host_out, h->B[mode], h->J[mode], h->R,
+                           h->sh.R16);
+}
+
+extern "C" ft_status ft_set_params(ft_handle *h, int mode, int which,
+                                   const float *host_in) {
+    CHECK_HANDLE(h);
+    if (mode < 0 || mode >= h->N || (which != 0 && which != 1) || !host_in)
+        return fail(h, FT_EINVAL, "bad mode/which/in");
+    if (which == 0)
+        return upload_padded(h, h->A[mode], host_in, h->dims[mode], h->J[mode],
+                             h->sh.J4);
+    return upload_padded(h, h->B[mode], host_in, h->J[mode], h->R, h->sh.R16);
+}
+
+// ------------------------------------------------------------------ builder output
+extern "C" ft_status ft_get_epoch_order(ft_handle *h, int64_t *perm_out) {
+    CHECK_HANDLE(h);
+    if (!perm_out) return fail(h, FT_EINVAL, "perm_out is NULL");
+    if (!h->prepared) return fail(h, FT_ESTATE, "no prepared epoch");
+    const int64_t nnz = h->nnz[FT_TRAIN];
+    std::vector<uint32_t> p((size_t)nnz);
+    HIPCHK(h, hipMemcpyAsync(p.data(), h->perm, sizeof(uint32_t) * nnz,
+                             hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    for (int64_t i = 0; i < nnz; ++i) perm_out[i] = p[(size_t)i];
+    return FT_OK;
+}
+
+extern "C" ft_status ft_get_minibatch_sort(ft_handle *h, int64_t b, int mode,
+                                           int32_t *pos, int32_t *rows) {
+    CHECK_HANDLE(h);
+    if (!h->prepared) return fail(h, FT_ESTATE, "no prepared epoch");
+    const int64_t nmb = nminibatches(h);
+    if (b < 0 || b >= nmb || mode < 0 || mode >= h->N || !pos || !rows)
+        return fail(h, FT_EINVAL, "bad minibatch/mode/buffers");
+    const int64_t off = b * h->opt.minibatch;
+    const int64_t m = std::min<int64_t>(h->opt.minibatch, h->nnz[FT_TRAIN] - off);
+    HIPCHK(h, hipMemcpyAsync(pos, h->sv[h->sort_final][mode] + off,
+                             sizeof(int32_t) * m, hipMemcpyDeviceToHost,
+                             h->stream));
+    HIPCHK(h, hipMemcpyAsync(rows, h->sk[h->sort_final][mode] + off,
+                             sizeof(int32_t) * m, hipMemcpyDeviceToHost,
+                             h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    return FT_OK;
+}
+
+// ------------------------------------------------------------------ profiling
+extern "C" ft_status ft_profile_enable(ft_handle *h, int32_t on) {
+    CHECK_HANDLE(h);
+    h->prof = on != 0;
+    return FT_OK;
+}
+
+extern "C" ft_status ft_profile_reset(ft_handle *h) {
+    CHECK_HANDLE(h);
+    ft_status st = prof_collect(h);
+    for (int k = 0; k < FT_K_COUNT; ++k) {
+        h->launches[k] = 0;
+        h->ms[k] = 0.0;
+    }
+    return st;
+}
+
+extern "C" ft_status ft_profile_get(ft_handle *h, int32_t kernel,
+                                    int64_t *launches, double *total_ms) {
+    CHECK_HANDLE(h);
+    if (kernel < 0 || kernel >= FT_K_COUNT || !launches || !total_ms)
+        return fail(h, FT_EINVAL, "bad kernel id or output");
+    ft_status st = prof_collect(h);
+    if (st != FT_OK) return st;
+    *launches = h->launches[kernel];
+    *total_ms = h->ms[kernel];
+    return FT_OK;
+}

@@ -1,0 +1,136 @@
+// ft_internal.h -- shapes, argument blocks and launchers shared by the host
+// runtime (ft_api.cpp) and the HIP kernels of the sparse FastTucker library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ft {
+
+constexpr int kMaxOrder = 5;
+constexpr int kMaxJ = 32;
+constexpr int kMaxR = 32;
+
+// Sorted segmented reduction: rows are summed over fixed chunks of this many
+// sorted samples; segments that cross a chunk edge are finished by a fix-up.
+constexpr int kSegChunk = 64;
+
+// Mode-sorted minibatch builder: LSD radix sort, 8-bit digits, 2048-element
+// tiles aligned to minibatch starts.
+constexpr int kSortThreads = 256;
+constexpr int kSortRounds = 8;
+constexpr int kSortTile = kSortThreads * kSortRounds;
+constexpr int kRadix = 256;
+
+// Padded shape. A^(n) is stored I_n x J4 (row stride J4 = max J_n rounded up
+// to 4); B^(n) is stored J4 x R16 (R rounded up to 16). Padding is zero and
+// stays zero under every update.
+struct Shape {
+    int N;
+    int J4;
+    int R16;
+};
+
+// ---------------------------------------------------------------- builder
+hipError_t launch_epoch_order(uint32_t *perm, int64_t n, uint64_t key,
+                              hipStream_t s);
+hipError_t launch_copy_order(uint32_t *perm, const int64_t *src, int64_t n,
+                             hipStream_t s);
+hipError_t launch_permute(int N, const int32_t *const *idx, const float *val,
+                          const uint32_t *perm, int64_t nnz,
+                          int32_t *const *pidx, float *pval, hipStream_t s);
+
+struct SortPass {
+    int N;
+    int64_t nnz;
+    int64_t M;           // segment (minibatch) length
+    int nseg;
+    int tiles_per_seg;   // tiles of a full segment
+    int shift;           // digit = (key >> shift) & 255
+    const uint32_t *key_in[kMaxOrder];
+    const uint32_t *val_in[kMaxOrder];   // nullptr: payload = position in segment
+    uint32_t *key_out[kMaxOrder];
+    uint32_t *val_out[kMaxOrder];
+    uint32_t *counts;    // [N][nseg][kRadix][tiles_per_seg]
+};
+hipError_t launch_sort_pass(const SortPass &p, hipStream_t s);
+
+// ---------------------------------------------------------------- factor phase
+struct FactorArgs {
+    const int32_t *idx[kMaxOrder];  // coordinates of the minibatch (m entries)
+    const float *val;
+    int32_t m;
+    const float *A[kMaxOrder];
+    const float *B[kMaxOrder];
+    float *G;                        // [N][m][J4] per-sample row gradients
+    double *loss_part;               // one per block
+};
+hipError_t launch_factor_grad(const Shape &sh, const FactorArgs &a, int *nblocks,
+                              hipStream_t s);
+int factor_grad_blocks(int32_t m);
+
+struct SegArgs {
+    int N;
+    int J4;
+    int32_t m;
+    int nchunks;                      // ceil(m / kSegChunk)
+    const uint32_t *rows[kMaxOrder];  // sorted rows of the minibatch
+    const uint32_t *pos[kMaxOrder];   // sorted in-minibatch positions
+    const float *G;                   // [N][m][J4]
+    float *A[kMaxOrder];
+    float *first;                     // [N][nchunks][J4]
+    float *last;                      // [N][nchunks][J4]
+    float lr, lam;
+    int mean;                         // FT_ROW_MEAN
+    int apply;                        // 1: update A; 0: write grad/count
+    float *grad[kMaxOrder];           // dense I_n x J4 (apply == 0)
+    int32_t *count[kMaxOrder];        // I_n (apply == 0)
+};
+hipError_t launch_seg_reduce(const SegArgs &a, hipStream_t s);
+hipError_t launch_seg_fixup(const SegArgs &a, hipStream_t s);
+
+hipError_t launch_sum_blocks(const double *part, int nper, int ngroups,
+                             double *out, hipStream_t s);
+
+// ---------------------------------------------------------------- core phase
+struct CoreArgs {
+    const int32_t *idx[kMaxOrder];
+    const float *val;
+    int64_t count;
+    const float *A[kMaxOrder];
+    const float *B[kMaxOrder];
+    float *part;          // [nblocks][N][J4][R16]
+    double *loss_part;    // [nblocks]
+};
+int core_grad_blocks(int64_t count);
+hipError_t launch_core_grad(const Shape &sh, const CoreArgs &a, int nblocks,
+                            hipStream_t s);
+
+struct CoreUpdateArgs {
+    const float *part;    // [nblocks][N][J4][R16]
+    int nblocks;
+    float *B[kMaxOrder];
+    float *grad_out;      // [N][J4][R16] or nullptr
+    double inv_count;     // 1 / |Omega| (or 1 / minibatch size)
+    float lr, lam;
+    int apply;
+};
+hipError_t launch_core_update(const Shape &sh, const CoreUpdateArgs &a,
+                              hipStream_t s);
+
+// ---------------------------------------------------------------- evaluation
+struct EvalArgs {
+    const int32_t *idx[kMaxOrder];
+    const float *val;
+    int64_t count;
+    const float *A[kMaxOrder];
+    const float *B[kMaxOrder];
+    double *part;         // [nblocks][2]: sum r^2, sum |r|
+};
+int eval_blocks(int64_t count);
+hipError_t launch_eval(const Shape &sh, const EvalArgs &a, int nblocks,
+                       hipStream_t s);
+hipError_t launch_sumsq(const float *x, int64_t n, double *part, int nblocks,
+                        hipStream_t s);
+
+}  // namespace ft

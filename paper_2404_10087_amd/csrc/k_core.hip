@@ -1,0 +1,234 @@
+// k_core.hip -- core phase of FastTuckerPlus (Algorithm 5; Eq. (13) in the
+// matrix form of Eq. (15)).
+//
+// core_grad_kernel: one wave per 16-sample tile, A and B fixed. C^(n) =
+// A_Psi^(n) B^(n) is formed on the matrix cores in the "sample-row" layout
+// (lane column = r), D^(n) by prefix/suffix products, xhat by a 16-lane
+// reduction, and the core gradient
+//     Grad^(n) += E^(n)T D^(n),   E^(n) = r (*) A_Psi^(n)
+// by a second matrix-core product whose contraction runs over the 16 samples
+// of the tile. Every wave keeps its Grad^(n) in accumulator registers across
+// all of its tiles (the register accumulation of Algorithm 5); a block sums its
+// four waves in a fixed order and writes one partial per block.
+//
+// core_update_kernel: sums the block partials in a fixed order (no atomics)
+// and applies B^(n) <- B^(n) - lr_B (Grad^(n) / count + lambda_B B^(n)).
+#include "ft_internal.h"
+#include "mfma_tile.h"
+
+namespace ft {
+
+constexpr int kCoreMaxBlocks = 1024;
+
+int core_grad_blocks(int64_t count) {
+    int64_t ntiles = (count + 15) / 16;
+    int64_t blocks = (ntiles + 3) / 4;
+    if (blocks > kCoreMaxBlocks) blocks = kCoreMaxBlocks;
+    return blocks < 1 ? 1 : (int)blocks;
+}
+
+template <int N, int KQ, int RB>
+__global__ __launch_bounds__(256) void core_grad_kernel(CoreArgs a,
+                                                        int64_t ntiles) {
+    constexpr int J4 = 4 * KQ;
+    constexpr int R16 = 16 * RB;
+    constexpr int JB = (KQ + 3) / 4;
+    extern __shared__ float lds[];   // [4 waves][N][J4][R16]
+    const int lane = threadIdx.x & 63, q = lane >> 4, c = lane & 15;
+    const int wave = threadIdx.x >> 6;
+
+    float bop[N][RB][KQ];   // B-operand: B[k = KQ*q + t][r = 16*rb + c]
+#pragma unroll
+    for (int n = 0; n < N; ++n)
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int t = 0; t < KQ; ++t)
+                bop[n][rb][t] = a.B[n][(KQ * q + t) * R16 + 16 * rb + c];
+
+    floatx4 grad[N][JB][RB];
+#pragma unroll
+    for (int n = 0; n < N; ++n)
+#pragma unroll
+        for (int jb = 0; jb < JB; ++jb)
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb)
+                grad[n][jb][rb] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+    double loss = 0.0;
+    const int64_t nwaves = (int64_t)gridDim.x * 4;
+    for (int64_t tile = (int64_t)blockIdx.x * 4 + wave; tile < ntiles;
+         tile += nwaves) {
+        const int64_t base = tile * 16;
+        const int64_t last = a.count - 1;
+        const int64_t ps = base + c <= last ? base + c : last;
+
+        float arow[N][KQ];
+#pragma unroll
+        for (int n = 0; n < N; ++n) {
+            const int row = a.idx[n][ps];
+            load_row_part<KQ>(a.A[n] + (int64_t)row * J4 + KQ * q, arow[n]);
+        }
+        floatx4 C[N][RB];
+#pragma unroll
+        for (int n = 0; n < N; ++n)
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) {
+                floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int t = 0; t < KQ; ++t)
+                    acc = mfma_16x16x4(arow[n][t], bop[n][rb][t], acc);
+                C[n][rb] = acc;   // C[s = 4q + v][r = 16 rb + c]
+            }
+        floatx4 D[N][RB];
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+            floatx4 pre = {1.f, 1.f, 1.f, 1.f};
+#pragma unroll
+            for (int n = 0; n < N; ++n) {
+                D[n][rb] = pre;
+                pre *= C[n][rb];
+            }
+            floatx4 suf = {1.f, 1.f, 1.f, 1.f};
+#pragma unroll
+            for (int n = N - 1; n >= 0; --n) {
+                D[n][rb] *= suf;
+                suf *= C[n][rb];
+            }
+        }
+        float r[4];
+        int64_t sv[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            float xh = 0.f;
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) xh += C[0][rb][v] * D[0][rb][v];
+            xh = sum_row16(xh);
+            const int64_t s = base + 4 * q + v;
+            sv[v] = s <= last ? s : last;
+            r[v] = s <= last ? xh - a.val[sv[v]] : 0.f;
+            if (c == 0 && s <= last) loss += 0.5 * (double)r[v] * (double)r[v];
+        }
+#pragma unroll
+        for (int n = 0; n < N; ++n) {
+            int rows4[4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) rows4[v] = a.idx[n][sv[v]];
+#pragma unroll
+            for (int jb = 0; jb < JB; ++jb) {
+                const int j = 16 * jb + c;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const float e =
+                        j < J4 ? r[v] * a.A[n][(int64_t)rows4[v] * J4 + j] : 0.f;
+#pragma unroll
+                    for (int rb = 0; rb < RB; ++rb)
+                        grad[n][jb][rb] =
+                            mfma_16x16x4(e, D[n][rb][v], grad[n][jb][rb]);
+                }
+            }
+        }
+    }
+
+    // grad[n][jb][rb][v] holds Grad^(n)[j = 16 jb + 4q + v][r = 16 rb + c]
+    float *mine = lds + wave * (N * J4 * R16);
+#pragma unroll
+    for (int n = 0; n < N; ++n)
+#pragma unroll
+        for (int jb = 0; jb < JB; ++jb)
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int j = 16 * jb + 4 * q + v;
+                    if (j < J4)
+                        mine[(n * J4 + j) * R16 + 16 * rb + c] =
+                            grad[n][jb][rb][v];
+                }
+    __syncthreads();
+    constexpr int E = N * J4 * R16;
+    float *out = a.part + (int64_t)blockIdx.x * E;
+    for (int e = threadIdx.x; e < E; e += 256)
+        out[e] = ((lds[e] + lds[E + e]) + lds[2 * E + e]) + lds[3 * E + e];
+    const double tot = block_sum_256(loss);
+    if (threadIdx.x == 0) a.loss_part[blockIdx.x] = tot;
+}
+
+template <int N, int KQ, int RB>
+static hipError_t launch_cg(const CoreArgs &a, int blocks, hipStream_t s) {
+    const int64_t ntiles = (a.count + 15) / 16;
+    const size_t lds = sizeof(float) * 4 * N * (4 * KQ) * (16 * RB);
+    hipLaunchKernelGGL((core_grad_kernel<N, KQ, RB>), dim3(blocks), dim3(256),
+                       lds, s, a, ntiles);
+    return hipGetLastError();
+}
+
+template <int N, int KQ>
+static hipError_t launch_cg_r(const Shape &sh, const CoreArgs &a, int blocks,
+                              hipStream_t s) {
+    return sh.R16 == 16 ? launch_cg<N, KQ, 1>(a, blocks, s)
+                        : launch_cg<N, KQ, 2>(a, blocks, s);
+}
+
+template <int N>
+static hipError_t launch_cg_j(const Shape &sh, const CoreArgs &a, int blocks,
+                              hipStream_t s) {
+    switch (sh.J4) {
+    case 4: return launch_cg_r<N, 1>(sh, a, blocks, s);
+    case 8: return launch_cg_r<N, 2>(sh, a, blocks, s);
+    case 12: return launch_cg_r<N, 3>(sh, a, blocks, s);
+    case 16: return launch_cg_r<N, 4>(sh, a, blocks, s);
+    case 20: return launch_cg_r<N, 5>(sh, a, blocks, s);
+    case 24: return launch_cg_r<N, 6>(sh, a, blocks, s);
+    case 28: return launch_cg_r<N, 7>(sh, a, blocks, s);
+    case 32: return launch_cg_r<N, 8>(sh, a, blocks, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_core_grad(const Shape &sh, const CoreArgs &a, int nblocks,
+                            hipStream_t s) {
+    switch (sh.N) {
+    case 2: return launch_cg_j<2>(sh, a, nblocks, s);
+    case 3: return launch_cg_j<3>(sh, a, nblocks, s);
+    case 4: return launch_cg_j<4>(sh, a, nblocks, s);
+    case 5: return launch_cg_j<5>(sh, a, nblocks, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+// 64 consecutive elements per block; four slices of the partials each summed
+// in increasing block order, then the slices in order.
+__global__ __launch_bounds__(256) void core_update_kernel(CoreUpdateArgs a,
+                                                          int E, int J4,
+                                                          int R16) {
+    __shared__ float part[4][64];
+    const int el = threadIdx.x & 63, sl = threadIdx.x >> 6;
+    const int e = blockIdx.x * 64 + el;
+    float acc = 0.f;
+    if (e < E)
+        for (int b = sl; b < a.nblocks; b += 4)
+            acc += a.part[(int64_t)b * E + e];
+    part[sl][el] = acc;
+    __syncthreads();
+    if (sl == 0 && e < E) {
+        const float g = ((part[0][el] + part[1][el]) + part[2][el]) + part[3][el];
+        if (a.grad_out) a.grad_out[e] = g;
+        if (a.apply) {
+            const int n = e / (J4 * R16);
+            float *bp = a.B[n] + (e - n * J4 * R16);
+            const float bv = *bp;
+            *bp = bv - a.lr * (float)((double)g * a.inv_count + (double)a.lam * bv);
+        }
+    }
+}
+
+hipError_t launch_core_update(const Shape &sh, const CoreUpdateArgs &a,
+                              hipStream_t s) {
+    const int E = sh.N * sh.J4 * sh.R16;
+    hipLaunchKernelGGL(core_update_kernel, dim3((E + 63) / 64), dim3(256), 0, s,
+                       a, E, sh.J4, sh.R16);
+    return hipGetLastError();
+}
+
+}  // namespace ft

@@ -1,0 +1,346 @@
+// k_factor.hip -- factor phase of FastTuckerPlus on CDNA4 (Algorithm 3 first
+// loop, update rule Eq. (12) in the matrix form of Eq. (14)).
+//
+// factor_grad_kernel: one wave per 16-sample tile. For every sample s and
+// mode n it gathers the row a^(n)_{i_n}, forms C^(n)T = B^(n)T A_Psi^(n)T on the
+// matrix cores (samples along the lane's column, r along the accumulator
+// rows), the leave-one-out products D^(n) = prod_{k != n} C^(k) (prefix and
+// suffix products, in registers), xhat = C^(1) . D^(1) (sum over r by lane
+// shuffles), r = xhat - x, and the row gradient
+//     g^(n)_s = r_s * B^(n) d^(n)_s            (Eq. (8)),
+// again on the matrix cores as G^T = B^(n) (r (*) D^(n))^T, which lands in the
+// natural "sample-column" layout so it is stored as float4 rows with no
+// transpose. All reads use A and B as they stand at the minibatch start.
+//
+// seg_reduce_kernel / seg_fixup_kernel: the deterministic row reduction.
+// The builder has sorted every minibatch's samples by row (ties in minibatch
+// order). Each group of lanes (one lane per column j) walks a fixed chunk of
+// kSegChunk sorted samples in order, summing g per row; rows whose samples
+// all lie in the chunk are finished there, the partial sums of rows that
+// cross a chunk edge are finished by the fix-up kernel in chunk order. A
+// finished row takes
+//     G = sum_s g_s + k * lambda_A * a,   a <- a - lr_A * G   (or G / k)
+// No floating-point atomics are used, so results are bitwise reproducible.
+#include "ft_internal.h"
+#include "mfma_tile.h"
+
+namespace ft {
+
+constexpr int kFactorThreads = 256;
+constexpr int kFactorMaxBlocks = 2048;
+
+int factor_grad_blocks(int32_t m) {
+    int ntiles = (m + 15) / 16;
+    int blocks = (ntiles + 3) / 4;
+    if (blocks > kFactorMaxBlocks) blocks = kFactorMaxBlocks;
+    return blocks < 1 ? 1 : blocks;
+}
+
+template <int N, int KQ, int RB>
+__global__ __launch_bounds__(kFactorThreads) void factor_grad_kernel(
+    FactorArgs a, int ntiles) {
+    constexpr int J4 = 4 * KQ;
+    constexpr int R16 = 16 * RB;
+    constexpr int JB = (KQ + 3) / 4;   // 16-row output blocks of J4
+    const int lane = threadIdx.x & 63, q = lane >> 4, c = lane & 15;
+
+    // A-operands: B^(n)T for the contraction over j, B^(n) for the one over r.
+    float bf[N][RB][KQ];
+    float bb[N][JB][RB][4];
+#pragma unroll
+    for (int n = 0; n < N; ++n) {
+        const float *B = a.B[n];
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int t = 0; t < KQ; ++t)
+                bf[n][rb][t] = B[(KQ * q + t) * R16 + 16 * rb + c];
+#pragma unroll
+        for (int jb = 0; jb < JB; ++jb) {
+            const int j = 16 * jb + c;
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    bb[n][jb][rb][v] =
+                        j < J4 ? B[j * R16 + 16 * rb + 4 * q + v] : 0.f;
+        }
+    }
+
+    double loss = 0.0;
+    const int nwaves = gridDim.x * (kFactorThreads / 64);
+    for (int tile = blockIdx.x * (kFactorThreads / 64) + (threadIdx.x >> 6);
+         tile < ntiles; tile += nwaves) {
+        const int p = tile * 16 + c;
+        const bool valid = p < a.m;
+        const int ps = valid ? p : a.m - 1;
+
+        float arow[N][KQ];
+#pragma unroll
+        for (int n = 0; n < N; ++n) {
+            const int row = a.idx[n][ps];
+            load_row_part<KQ>(a.A[n] + (int64_t)row * J4 + KQ * q, arow[n]);
+        }
+        const float x = a.val[ps];
+
+        floatx4 C[N][RB];
+#pragma unroll
+        for (int n = 0; n < N; ++n)
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) {
+                floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int t = 0; t < KQ; ++t)
+                    acc = mfma_16x16x4(bf[n][rb][t], arow[n][t], acc);
+                C[n][rb] = acc;
+            }
+
+        floatx4 D[N][RB];
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+            floatx4 pre = {1.f, 1.f, 1.f, 1.f};
+#pragma unroll
+            for (int n = 0; n < N; ++n) {
+                D[n][rb] = pre;
+                pre *= C[n][rb];
+            }
+            floatx4 suf = {1.f, 1.f, 1.f, 1.f};
+#pragma unroll
+            for (int n = N - 1; n >= 0; --n) {
+                D[n][rb] *= suf;
+                suf *= C[n][rb];
+            }
+        }
+
+        float xh = 0.f;
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) xh += C[0][rb][v] * D[0][rb][v];
+        xh = sum_quads(xh);
+        const float r = valid ? xh - x : 0.f;
+        if (valid && q == 0) loss += 0.5 * (double)r * (double)r;
+
+#pragma unroll
+        for (int n = 0; n < N; ++n) {
+            float *Gn = a.G + ((int64_t)n * a.m + p) * J4;
+#pragma unroll
+            for (int jb = 0; jb < JB; ++jb) {
+                floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v)
+                        acc = mfma_16x16x4(bb[n][jb][rb][v],
+                                           r * D[n][rb][v], acc);
+                const int j0 = 16 * jb + 4 * q;
+                if (valid && j0 < J4)
+                    *reinterpret_cast<floatx4 *>(Gn + j0) = acc;
+            }
+        }
+    }
+    const double tot = block_sum_256(loss);
+    if (threadIdx.x == 0) a.loss_part[blockIdx.x] = tot;
+}
+
+template <int N, int KQ, int RB>
+static hipError_t launch_fg(const FactorArgs &a, int blocks, hipStream_t s) {
+    const int ntiles = (a.m + 15) / 16;
+    hipLaunchKernelGGL((factor_grad_kernel<N, KQ, RB>), dim3(blocks),
+                       dim3(kFactorThreads), 0, s, a, ntiles);
+    return hipGetLastError();
+}
+
+template <int N, int KQ>
+static hipError_t launch_fg_r(const Shape &sh, const FactorArgs &a, int blocks,
+                              hipStream_t s) {
+    return sh.R16 == 16 ? launch_fg<N, KQ, 1>(a, blocks, s)
+                        : launch_fg<N, KQ, 2>(a, blocks, s);
+}
+
+template <int N>
+static hipError_t launch_fg_j(const Shape &sh, const FactorArgs &a, int blocks,
+                              hipStream_t s) {
+    switch (sh.J4) {
+    case 4: return launch_fg_r<N, 1>(sh, a, blocks, s);
+    case 8: return launch_fg_r<N, 2>(sh, a, blocks, s);
+    case 12: return launch_fg_r<N, 3>(sh, a, blocks, s);
+    case 16: return launch_fg_r<N, 4>(sh, a, blocks, s);
+    case 20: return launch_fg_r<N, 5>(sh, a, blocks, s);
+    case 24: return launch_fg_r<N, 6>(sh, a, blocks, s);
+    case 28: return launch_fg_r<N, 7>(sh, a, blocks, s);
+    case 32: return launch_fg_r<N, 8>(sh, a, blocks, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_factor_grad(const Shape &sh, const FactorArgs &a, int *nblocks,
+                              hipStream_t s) {
+    const int blocks = factor_grad_blocks(a.m);
+    *nblocks = blocks;
+    switch (sh.N) {
+    case 2: return launch_fg_j<2>(sh, a, blocks, s);
+    case 3: return launch_fg_j<3>(sh, a, blocks, s);
+    case 4: return launch_fg_j<4>(sh, a, blocks, s);
+    case 5: return launch_fg_j<5>(sh, a, blocks, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+// ------------------------------------------------------------ row reduction
+__device__ __forceinline__ void finish_row(const SegArgs &a, int n, int j,
+                                           bool col, uint32_t row, float sum,
+                                           int cnt) {
+    if (!col) return;
+    float *ap = a.A[n] + (int64_t)row * a.J4 + j;
+    const float av = *ap;
+    float g = sum + (float)cnt * a.lam * av;
+    if (a.apply) {
+        if (a.mean) g /= (float)cnt;
+        *ap = av - a.lr * g;
+    } else {
+        a.grad[n][(int64_t)row * a.J4 + j] = g;
+        if (j == 0) a.count[n][row] = cnt;
+    }
+}
+
+template <int LP>
+__global__ __launch_bounds__(256) void seg_reduce_kernel(SegArgs a) {
+    const int g = blockIdx.x * (256 / LP) + threadIdx.x / LP;
+    const int j = threadIdx.x % LP;
+    if (g >= a.N * a.nchunks) return;
+    const int n = g / a.nchunks, c = g % a.nchunks;
+    const int i0 = c * kSegChunk;
+    const int i1 = min(i0 + kSegChunk, a.m);
+    const uint32_t *rows = a.rows[n];
+    const uint32_t *pos = a.pos[n];
+    const float *G = a.G + (int64_t)n * a.m * a.J4;
+    const bool col = j < a.J4;
+    const uint32_t first_row = rows[i0];
+    const bool starts_before = i0 > 0 && rows[i0 - 1] == first_row;
+    const bool continues_after = i1 < a.m && rows[i1] == rows[i1 - 1];
+    float *first = a.first + ((int64_t)n * a.nchunks + c) * a.J4 + j;
+    float *last = a.last + ((int64_t)n * a.nchunks + c) * a.J4 + j;
+
+    float acc = 0.f;
+    int cnt = 0;
+    uint32_t cur = first_row;
+    bool is_first = true;
+    for (int base = i0; base < i1; base += 8) {
+        uint32_t rr[8];
+        float gg[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int i = base + u;
+            rr[u] = i < i1 ? rows[i] : cur;
+            gg[u] = (i < i1 && col) ? G[(int64_t)pos[i] * a.J4 + j] : 0.f;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            if (base + u >= i1) break;
+            if (rr[u] != cur) {
+                // close the fragment of row `cur`; it cannot continue past the
+                // chunk, so it is finished here unless it started before
+                if (is_first && starts_before) {
+                    if (col) *first = acc;
+                } else {
+                    finish_row(a, n, j, col, cur, acc, cnt);
+                }
+                acc = 0.f;
+                cnt = 0;
+                cur = rr[u];
+                is_first = false;
+            }
+            acc += gg[u];
+            ++cnt;
+        }
+    }
+    const bool span_before = is_first && starts_before;
+    if (!span_before && !continues_after) {
+        finish_row(a, n, j, col, cur, acc, cnt);
+    } else if (col) {
+        if (is_first) *first = acc;
+        *last = acc;
+    }
+}
+
+__global__ __launch_bounds__(256) void seg_fixup_kernel(SegArgs a, int LP) {
+    const int g = blockIdx.x * (256 / LP) + threadIdx.x / LP;
+    const int j = threadIdx.x % LP;
+    if (g >= a.N * a.nchunks) return;
+    const int n = g / a.nchunks, c = g % a.nchunks;
+    const int i0 = c * kSegChunk;
+    if (i0 == 0) return;
+    const uint32_t *rows = a.rows[n];
+    const uint32_t row = rows[i0];
+    if (rows[i0 - 1] != row) return;              // segment starts in c
+    const int i1 = min(i0 + kSegChunk, a.m);
+    if (i1 < a.m && rows[i1 - 1] == row && rows[i1] == row)
+        return;                                   // segment ends after c
+    int lo = 0, hi = i0;                          // first sorted index of row
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (rows[mid] < row) lo = mid + 1; else hi = mid;
+    }
+    const int start = lo;
+    int end = i0;
+    while (end < i1 && rows[end] == row) ++end;
+    const bool col = j < a.J4;
+    if (!col) return;
+    const int c0 = start / kSegChunk;
+    const float *first = a.first + (int64_t)n * a.nchunks * a.J4 + j;
+    const float *last = a.last + (int64_t)n * a.nchunks * a.J4 + j;
+    float acc = last[(int64_t)c0 * a.J4];
+    for (int cc = c0 + 1; cc <= c; ++cc) acc += first[(int64_t)cc * a.J4];
+    finish_row(a, n, j, col, row, acc, end - start);
+}
+
+static int lanes_per_group(int J4) {
+    int lp = 4;
+    while (lp < J4) lp <<= 1;
+    return lp;
+}
+
+hipError_t launch_seg_reduce(const SegArgs &a, hipStream_t s) {
+    const int lp = lanes_per_group(a.J4);
+    const int groups = a.N * a.nchunks;
+    const int blocks = (groups + 256 / lp - 1) / (256 / lp);
+    switch (lp) {
+    case 4: hipLaunchKernelGGL(seg_reduce_kernel<4>, dim3(blocks), dim3(256), 0, s, a); break;
+    case 8: hipLaunchKernelGGL(seg_reduce_kernel<8>, dim3(blocks), dim3(256), 0, s, a); break;
+    case 16: hipLaunchKernelGGL(seg_reduce_kernel<16>, dim3(blocks), dim3(256), 0, s, a); break;
+    case 32: hipLaunchKernelGGL(seg_reduce_kernel<32>, dim3(blocks), dim3(256), 0, s, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_seg_fixup(const SegArgs &a, hipStream_t s) {
+    const int lp = lanes_per_group(a.J4);
+    const int groups = a.N * a.nchunks;
+    const int blocks = (groups + 256 / lp - 1) / (256 / lp);
+    hipLaunchKernelGGL(seg_fixup_kernel, dim3(blocks), dim3(256), 0, s, a, lp);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------ block sums
+// out[g] = sum of part[g*nper .. g*nper + nper) in a fixed order.
+__global__ __launch_bounds__(256) void sum_blocks_kernel(const double *part,
+                                                         int nper,
+                                                         double *out) {
+    const double *p = part + (int64_t)blockIdx.x * nper;
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < nper; i += 256) acc += p[i];
+    const double t = block_sum_256(acc);
+    if (threadIdx.x == 0) out[blockIdx.x] = t;
+}
+
+hipError_t launch_sum_blocks(const double *part, int nper, int ngroups,
+                             double *out, hipStream_t s) {
+    if (ngroups <= 0) return hipSuccess;
+    hipLaunchKernelGGL(sum_blocks_kernel, dim3(ngroups), dim3(256), 0, s, part,
+                       nper, out);
+    return hipGetLastError();
+}
+
+}  // namespace ft

@@ -99,6 +99,6 @@ CONFIGS = {
 }
 
 
-def get(name, **overrides):
-    w = CONFIGS[name]
+def get(key, **overrides):
+    w = CONFIGS[key]
     return replace(w, **overrides) if overrides else w

@@ -1,0 +1,103 @@
+"""The C-ABI boundary on a host without a GPU: the library loads, exports
+every entry point that include/ft.h declares, and validates arguments before
+touching the device."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2404_10087_amd import _lib
+from tests import _ref
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "ft.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ft_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declarations_are_exported():
+    lib = C.CDLL(_lib.LIB_PATH)
+    names = _declared()
+    assert len(names) >= 25
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    # the binding declares exactly the header's entry points
+    assert sorted(_lib.SIGNATURES) == names
+
+
+def test_options_struct_layout():
+    assert C.sizeof(_lib.Options) == 72
+    lib = _lib.load()
+    o = _lib.Options()
+    assert lib.ft_default_options(C.byref(o)) == 0
+    assert o.minibatch == 512 and o.deterministic == 1
+    assert o.lr_A == 0.01 and o.lambda_B == 1e-3
+    assert o.reshuffle_each_epoch == 1
+
+
+def _create(order, dims, J, R):
+    lib = _lib.load()
+    d = np.array(dims, dtype=np.int64)
+    j = np.array(J, dtype=np.int32)
+    h = C.c_void_p(12345)
+    st = lib.ft_create(order, d.ctypes.data_as(C.POINTER(C.c_int64)),
+                       j.ctypes.data_as(C.POINTER(C.c_int32)), R, 7,
+                       C.byref(h))
+    return st, h, lib.ft_last_error(None).decode()
+
+
+@pytest.mark.parametrize("order,dims,J,R,needle", [
+    (1, [10], [4], 4, "order"),
+    (6, [3] * 6, [2] * 6, 2, "order"),
+    (3, [10, 0, 10], [4, 4, 4], 4, "dims[1]"),
+    (3, [10, 10, 10], [4, 0, 4], 4, "J[1]"),
+    (3, [10, 10, 10], [4, 33, 4], 4, "J[1]"),
+    (3, [10, 10, 10], [4, 4, 4], 0, "R"),
+    (3, [10, 10, 10], [4, 4, 4], 33, "R"),
+    (2, [2 ** 31, 5], [4, 4], 4, "dims[0]"),
+])
+def test_create_rejects_bad_arguments(order, dims, J, R, needle):
+    st, h, msg = _create(order, dims, J, R)
+    assert st == _lib.FT_EINVAL
+    assert h.value is None
+    assert needle in msg
+
+
+def test_null_arguments():
+    lib = _lib.load()
+    assert lib.ft_create(3, None, None, 4, 0, None) == _lib.FT_EINVAL
+    assert lib.ft_destroy(None) == _lib.FT_OK
+    assert lib.ft_set_options(None, None) == _lib.FT_EINVAL
+    assert lib.ft_epoch_factors(None, None) == _lib.FT_EINVAL
+    assert lib.ft_rmse(None, 0, None) == _lib.FT_EINVAL
+    assert lib.ft_default_options(None) == _lib.FT_EINVAL
+    assert lib.ft_last_error(None)
+
+
+def test_create_without_device_reports_edevice():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    st, h, msg = _create(3, [10, 10, 10], [4, 4, 4], 4)
+    assert st == _lib.FT_EDEVICE and h.value is None
+    assert "device" in msg
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 17, 100, 1000, 4097, 65537])
+def test_feistel_order_reference_is_a_permutation(n):
+    p = _ref.feistel_order(n, _ref.epoch_key(11, 3))
+    assert np.array_equal(np.sort(p), np.arange(n))
+    if n > 100:   # and it actually shuffles
+        assert np.mean(p == np.arange(n)) < 0.05
+
+
+def test_minibatch_sort_reference_is_stable():
+    rows = np.array([5, 3, 5, 1, 3, 3, 0], dtype=np.int32)
+    pos, srt = _ref.minibatch_sort(rows)
+    assert list(pos) == [6, 3, 1, 4, 5, 0, 2]
+    assert list(srt) == [0, 1, 3, 3, 3, 5, 5]

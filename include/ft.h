@@ -68,8 +68,12 @@ typedef struct {
     int32_t core_step;         /* ft_core_step                               */
     int32_t deterministic;     /* 1: sorted segmented reductions, no float
                                   atomics, bitwise reproducible;
-                                  0: Hogwild fast mode (per-sample updates
-                                  with atomics, no minibatch barrier)        */
+                                  0: Hogwild fast mode as in the paper's GPU
+                                  algorithm: 16-sample tiles update their
+                                  rows at once with float atomics, no
+                                  minibatch barrier, no builder; minibatch
+                                  must be a multiple of 16 and only frames
+                                  the per-minibatch losses                   */
     uint64_t shuffle_seed;     /* seed of the device-side epoch order        */
     int32_t reshuffle_each_epoch; /* 1: new order every epoch; 0: fixed     */
 } ft_options;
@@ -137,7 +141,10 @@ ft_status ft_num_minibatches(const ft_handle *h, int64_t *out);
  * residual and the row gradients (Eq. (8)) with all parameters as they stand
  * at the minibatch start, and update every touched row (Eq. (12), scaled by
  * row_scale). mb_loss (NULL or [ceil(nnz/M)]) receives sum r^2/2 of every
- * minibatch, r = xhat - x. Advances the epoch counter. */
+ * minibatch, r = xhat - x. Advances the epoch counter. In the fast mode the
+ * tiles run concurrently with immediate per-sample steps
+ * a <- a - lr_A (r B d + lambda_A a) (Eq. (12) applied per sample, Hogwild);
+ * row_scale does not apply. */
 ft_status ft_epoch_factors(ft_handle *h, double *mb_loss);
 
 /* Fine-grained form of ft_epoch_factors for verification:
@@ -193,6 +200,56 @@ ft_status ft_profile_enable(ft_handle *h, int32_t on);
 ft_status ft_profile_reset(ft_handle *h);
 ft_status ft_profile_get(ft_handle *h, int32_t kernel, int64_t *launches,
                          double *total_ms);
+
+/* ------------------------------------------------------------------------
+ * Stateless minibatch entry points (back the torch.autograd.Function).
+ * The caller owns every buffer (device memory) and the stream; nothing is
+ * allocated. The minibatch loss is L = sum_{s in Psi} r_s^2 / 2 with
+ * r = xhat - x (data term only; regularisation is left to the caller).
+ *   A[n]   device FP32, dims[n] x J4 row-major, J4 = max_n J_n rounded up to
+ *          a multiple of 4; columns J_n..J4-1 must be zero
+ *   B[n]   device FP32, J_n x R row-major
+ *   idx[n] device int32, m coordinates of mode n (range is the caller's
+ *          responsibility: indices must lie in [0, dims[n]))
+ *   val    device FP32, m values
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    int32_t order;       /* 2..5                                            */
+    int64_t dims[5];     /* I_n                                             */
+    int32_t J[5];        /* 1..32                                           */
+    int32_t R;           /* 1..32                                           */
+} ft_problem_desc;
+
+/* Bytes of device workspace that ft_mb_forward / ft_mb_backward need for a
+ * minibatch of m samples (1 <= m <= 2^30). */
+ft_status ft_mb_workspace_size(const ft_problem_desc *p, int64_t m,
+                               size_t *bytes);
+
+/* *loss_dev (device double) <- sum r^2 / 2 over the minibatch, reduced in
+ * FP64 in a fixed order (Eq. (3) forward). */
+ft_status ft_mb_forward(const ft_problem_desc *p, const float *const *A,
+                        const float *const *B, const int32_t *const *idx,
+                        const float *val, int64_t m, double *loss_dev,
+                        void *workspace, size_t ws_bytes, void *hip_stream);
+
+/* Gradients of g * L, g = *grad_out_dev (device FP32; NULL means 1), with
+ * c^(n) recomputed (nothing is kept from the forward call):
+ *   rows (Eq. (8)): the per-sample r_s B^(n) d^(n)_s summed per unique row in
+ *     a fixed order (the deterministic sorted segmented reduction). Sparse
+ *     form: uniq_rows[n] (device int32, capacity m) receives the touched rows
+ *     in increasing order, uniq_grad[n] (device FP32, capacity m x J4) their
+ *     gradient rows, n_uniq_dev[n] (device int64) their number. Dense form:
+ *     gradA[n] (device FP32, dims[n] x J4) is overwritten (zero for untouched
+ *     rows). Either form may be omitted by passing NULL arrays.
+ *   core (Eq. (9)): gradB[n] (device FP32, J_n x R) is overwritten.
+ * Bitwise reproducible (no floating-point atomics). */
+ft_status ft_mb_backward(const ft_problem_desc *p, const float *const *A,
+                         const float *const *B, const int32_t *const *idx,
+                         const float *val, int64_t m,
+                         const float *grad_out_dev, float *const *gradA,
+                         int32_t *const *uniq_rows, float *const *uniq_grad,
+                         int64_t *n_uniq_dev, float *const *gradB,
+                         void *workspace, size_t ws_bytes, void *hip_stream);
 
 #ifdef __cplusplus
 }

@@ -29,6 +29,11 @@ class Options(C.Structure):
                 ("reshuffle_each_epoch", C.c_int32)]
 
 
+class ProblemDesc(C.Structure):
+    _fields_ = [("order", C.c_int32), ("dims", C.c_int64 * 5),
+                ("J", C.c_int32 * 5), ("R", C.c_int32)]
+
+
 _H = C.c_void_p
 _i32p = C.POINTER(C.c_int32)
 _i64p = C.POINTER(C.c_int64)
@@ -64,6 +69,18 @@ SIGNATURES = {
     "ft_profile_enable": (C.c_int, [_H, C.c_int32]),
     "ft_profile_reset": (C.c_int, [_H]),
     "ft_profile_get": (C.c_int, [_H, C.c_int32, _i64p, _f64p]),
+    "ft_mb_workspace_size": (C.c_int, [C.POINTER(ProblemDesc), C.c_int64,
+                                       C.POINTER(C.c_size_t)]),
+    "ft_mb_forward": (C.c_int, [C.POINTER(ProblemDesc), C.c_void_p,
+                                C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
+                                C.c_void_p, C.c_void_p, C.c_size_t,
+                                C.c_void_p]),
+    "ft_mb_backward": (C.c_int, [C.POINTER(ProblemDesc), C.c_void_p,
+                                 C.c_void_p, C.c_void_p, C.c_void_p,
+                                 C.c_int64, C.c_void_p, C.c_void_p,
+                                 C.c_void_p, C.c_void_p, C.c_void_p,
+                                 C.c_void_p, C.c_void_p, C.c_size_t,
+                                 C.c_void_p]),
 }
 
 _lib = None

@@ -12,7 +12,7 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libft.so")
 SOURCES = ["ft_api.cpp", "k_builder.hip", "k_factor.hip", "k_core.hip",
-           "k_eval.hip"]
+           "k_eval.hip", "k_autograd.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-x", "hip", "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Wall", "-Wno-unused-function",

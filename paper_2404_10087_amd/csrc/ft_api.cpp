@@ -69,6 +69,8 @@ struct ft_handle {
     size_t mb_part_cap = 0;
     double *mb_loss = nullptr;
     size_t mb_loss_cap = 0;
+    double *tile_loss = nullptr;
+    size_t tile_loss_cap = 0;
 
     // core-phase / evaluation scratch
     float *core_part = nullptr;
@@ -234,6 +236,7 @@ static void release(ft_handle *h) {
     dfree(h->last);
     dfree(h->mb_part);
     dfree(h->mb_loss);
+    dfree(h->tile_loss);
     dfree(h->core_part);
     dfree(h->dpart);
     dfree(h->scal);
@@ -283,9 +286,13 @@ static ft_status check_options(ft_handle *h, const ft_options *o) {
     if (o->core_step != FT_CORE_PER_EPOCH &&
         o->core_step != FT_CORE_PER_MINIBATCH)
         return fail(h, FT_EINVAL, "core_step must be PER_EPOCH or PER_MINIBATCH");
-    if (o->deterministic != 1)
+    if (o->deterministic != 0 && o->deterministic != 1)
+        return fail(h, FT_EINVAL, "deterministic must be 0 or 1");
+    if (o->deterministic == 0 && o->minibatch % 16 != 0)
         return fail(h, FT_EINVAL,
-                    "the Hogwild fast mode is not available in this build");
+                    "the Hogwild fast mode needs a minibatch that is a "
+                    "multiple of the 16-sample tile, got %lld",
+                    (long long)o->minibatch);
     if (o->reshuffle_each_epoch != 0 && o->reshuffle_each_epoch != 1)
         return fail(h, FT_EINVAL, "reshuffle_each_epoch must be 0 or 1");
     return FT_OK;
@@ -663,9 +670,59 @@ static ft_status alloc_factor(ft_handle *h, int64_t nmb, int nper) {
     return FT_OK;
 }
 
+// Hogwild fast mode: order + permutation, then one persistent sweep over all
+// tiles with immediate atomic row updates (no builder, no minibatch barrier).
+static ft_status epoch_factors_fast(ft_handle *h, std::vector<double> &losses) {
+    const int64_t nnz = h->nnz[FT_TRAIN];
+    ft_status st = draw_order(h, 0);
+    if (st == FT_OK) st = permute_streams(h);
+    if (st != FT_OK) return st;
+    h->prepared = false;
+    const int64_t nmb = nminibatches(h);
+    const int64_t tpm = h->opt.minibatch / 16;
+    HIPCHK(h, ensure(&h->tile_loss, &h->tile_loss_cap, (size_t)(nmb * tpm)));
+    HIPCHK(h, ensure(&h->mb_loss, &h->mb_loss_cap, (size_t)nmb));
+    HIPCHK(h, hipMemsetAsync(h->tile_loss, 0, sizeof(double) * nmb * tpm,
+                             h->stream));
+    HogArgs ha{};
+    for (int n = 0; n < h->N; ++n) {
+        ha.idx[n] = h->pidx[n];
+        ha.A[n] = h->A[n];
+        ha.B[n] = h->B[n];
+    }
+    ha.val = h->pval;
+    ha.count = nnz;
+    ha.lr = (float)h->opt.lr_A;
+    ha.lam = (float)h->opt.lambda_A;
+    ha.tile_loss = h->tile_loss;
+    {
+        Launch L(h, FT_K_HOGWILD);
+        HIPCHK(h, launch_hogwild(h->sh, ha, h->stream));
+    }
+    HIPCHK(h, launch_sum_blocks(h->tile_loss, (int)tpm, (int)nmb, h->mb_loss,
+                                h->stream));
+    losses.resize((size_t)nmb);
+    HIPCHK(h, hipMemcpyAsync(losses.data(), h->mb_loss, sizeof(double) * nmb,
+                             hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    return FT_OK;
+}
+
 extern "C" ft_status ft_epoch_factors(ft_handle *h, double *mb_loss) {
     CHECK_HANDLE(h);
     if (h->nnz[FT_TRAIN] < 1) return fail(h, FT_ESTATE, "no training set");
+    if (!h->opt.deterministic) {
+        std::vector<double> losses;
+        ft_status st = epoch_factors_fast(h, losses);
+        if (st != FT_OK) return st;
+        h->epoch += 1;
+        if (mb_loss)
+            std::memcpy(mb_loss, losses.data(), sizeof(double) * losses.size());
+        for (double l : losses)
+            if (!std::isfinite(l))
+                return fail(h, FT_ENONFINITE, "a minibatch loss is not finite");
+        return FT_OK;
+    }
     const bool reuse = h->prepared && !h->opt.reshuffle_each_epoch &&
                        h->prepared_M == h->opt.minibatch;
     if (!reuse) {
@@ -1028,5 +1085,287 @@ extern "C" ft_status ft_profile_get(ft_handle *h, int32_t kernel,
     if (st != FT_OK) return st;
     *launches = h->launches[kernel];
     *total_ms = h->ms[kernel];
+    return FT_OK;
+}
+
+// ------------------------------------------------------------------ stateless
+namespace {
+struct MbLayout {
+    size_t bpad, G, sk0, sk1, sv0, sv1, counts, first, last, ordinal,
+        tile_count, total, core_part, dpart, bytes;
+    int tps, nch, ntiles_scan, nb_core, nb_fact, nb_eval;
+    Shape sh;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+ft_status check_desc(const ft_problem_desc *p, int64_t m) {
+    if (!p) return fail(nullptr, FT_EINVAL, "problem descriptor is NULL");
+    if (p->order < 2 || p->order > kMaxOrder)
+        return fail(nullptr, FT_EINVAL, "order must be in [2, %d], got %d",
+                    kMaxOrder, p->order);
+    for (int n = 0; n < p->order; ++n) {
+        if (p->dims[n] < 1 || p->dims[n] > 0x7fffffffll)
+            return fail(nullptr, FT_EINVAL, "dims[%d] out of [1, 2^31)", n);
+        if (p->J[n] < 1 || p->J[n] > kMaxJ)
+            return fail(nullptr, FT_EINVAL, "J[%d] out of [1, %d]", n, kMaxJ);
+    }
+    if (p->R < 1 || p->R > kMaxR)
+        return fail(nullptr, FT_EINVAL, "R out of [1, %d]", kMaxR);
+    if (m < 1 || m > (1ll << 30))
+        return fail(nullptr, FT_EINVAL, "m must be in [1, 2^30], got %lld",
+                    (long long)m);
+    return FT_OK;
+}
+
+MbLayout mb_layout(const ft_problem_desc *p, int64_t m) {
+    MbLayout L{};
+    int jmax = 0;
+    for (int n = 0; n < p->order; ++n) jmax = std::max(jmax, (int)p->J[n]);
+    L.sh.N = p->order;
+    L.sh.J4 = (jmax + 3) / 4 * 4;
+    L.sh.R16 = (p->R + 15) / 16 * 16;
+    const size_t N = (size_t)p->order, J4 = L.sh.J4, R16 = L.sh.R16;
+    L.tps = (int)((m + kSortTile - 1) / kSortTile);
+    L.nch = (int)((m + kSegChunk - 1) / kSegChunk);
+    L.ntiles_scan = (int)((m + 2047) / 2048);
+    L.nb_core = core_grad_blocks(m);
+    L.nb_fact = factor_grad_blocks((int32_t)m);
+    L.nb_eval = eval_blocks(m);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off += align256(bytes);
+        return o;
+    };
+    L.bpad = take(sizeof(float) * N * J4 * R16);
+    L.G = take(sizeof(float) * N * m * J4);
+    L.sk0 = take(sizeof(uint32_t) * N * m);
+    L.sk1 = take(sizeof(uint32_t) * N * m);
+    L.sv0 = take(sizeof(uint32_t) * N * m);
+    L.sv1 = take(sizeof(uint32_t) * N * m);
+    L.counts = take(sizeof(uint32_t) * N * kRadix * L.tps);
+    L.first = take(sizeof(float) * N * L.nch * J4);
+    L.last = take(sizeof(float) * N * L.nch * J4);
+    L.ordinal = take(sizeof(uint32_t) * N * m);
+    L.tile_count = take(sizeof(uint32_t) * N * L.ntiles_scan);
+    L.total = take(sizeof(int64_t) * N);
+    L.core_part = take(sizeof(float) * L.nb_core * N * J4 * R16);
+    L.dpart = take(sizeof(double) *
+                   std::max<size_t>(2 * L.nb_eval,
+                                    std::max(L.nb_fact, L.nb_core)) + 64);
+    L.bytes = off;
+    return L;
+}
+
+template <typename T>
+T *at(void *ws, size_t off) {
+    return reinterpret_cast<T *>(static_cast<char *>(ws) + off);
+}
+
+#define HIPCHK0(expr) HIPCHK(nullptr, expr)
+
+ft_status pad_cores(const ft_problem_desc *p, const MbLayout &L,
+                    const float *const *B, void *ws, hipStream_t s,
+                    const float **Bp) {
+    for (int n = 0; n < p->order; ++n) {
+        float *dst = at<float>(ws, L.bpad) + (size_t)n * L.sh.J4 * L.sh.R16;
+        HIPCHK0(launch_pad_matrix(B[n], p->J[n], p->R, dst, L.sh.J4, L.sh.R16,
+                                  s));
+        Bp[n] = dst;
+    }
+    return FT_OK;
+}
+}  // namespace
+
+extern "C" ft_status ft_mb_workspace_size(const ft_problem_desc *p, int64_t m,
+                                          size_t *bytes) {
+    ft_status st = check_desc(p, m);
+    if (st != FT_OK) return st;
+    if (!bytes) return fail(nullptr, FT_EINVAL, "bytes is NULL");
+    *bytes = mb_layout(p, m).bytes;
+    return FT_OK;
+}
+
+static ft_status check_mb_args(const ft_problem_desc *p, const float *const *A,
+                               const float *const *B, const int32_t *const *idx,
+                               const float *val, int64_t m, void *ws,
+                               size_t ws_bytes) {
+    ft_status st = check_desc(p, m);
+    if (st != FT_OK) return st;
+    if (!A || !B || !idx || !val || !ws)
+        return fail(nullptr, FT_EINVAL, "A, B, idx, val or workspace is NULL");
+    for (int n = 0; n < p->order; ++n)
+        if (!A[n] || !B[n] || !idx[n])
+            return fail(nullptr, FT_EINVAL, "A[%d], B[%d] or idx[%d] is NULL",
+                        n, n, n);
+    const size_t need = mb_layout(p, m).bytes;
+    if (ws_bytes < need)
+        return fail(nullptr, FT_EINVAL, "workspace of %zu bytes < %zu needed",
+                    ws_bytes, need);
+    return FT_OK;
+}
+
+extern "C" ft_status ft_mb_forward(const ft_problem_desc *p,
+                                   const float *const *A, const float *const *B,
+                                   const int32_t *const *idx, const float *val,
+                                   int64_t m, double *loss_dev, void *workspace,
+                                   size_t ws_bytes, void *hip_stream) {
+    ft_status st = check_mb_args(p, A, B, idx, val, m, workspace, ws_bytes);
+    if (st != FT_OK) return st;
+    if (!loss_dev) return fail(nullptr, FT_EINVAL, "loss_dev is NULL");
+    hipStream_t s = (hipStream_t)hip_stream;
+    const MbLayout L = mb_layout(p, m);
+    const float *Bp[kMaxOrder] = {};
+    st = pad_cores(p, L, B, workspace, s, Bp);
+    if (st != FT_OK) return st;
+    EvalArgs ea{};
+    for (int n = 0; n < p->order; ++n) {
+        ea.idx[n] = idx[n];
+        ea.A[n] = A[n];
+        ea.B[n] = Bp[n];
+    }
+    ea.val = val;
+    ea.count = m;
+    ea.part = at<double>(workspace, L.dpart);
+    ea.half_square = 1;
+    HIPCHK0(launch_eval(L.sh, ea, L.nb_eval, s));
+    HIPCHK0(launch_sum_blocks(ea.part, L.nb_eval, 1, loss_dev, s));
+    return FT_OK;
+}
+
+extern "C" ft_status ft_mb_backward(
+    const ft_problem_desc *p, const float *const *A, const float *const *B,
+    const int32_t *const *idx, const float *val, int64_t m,
+    const float *grad_out_dev, float *const *gradA, int32_t *const *uniq_rows,
+    float *const *uniq_grad, int64_t *n_uniq_dev, float *const *gradB,
+    void *workspace, size_t ws_bytes, void *hip_stream) {
+    ft_status st = check_mb_args(p, A, B, idx, val, m, workspace, ws_bytes);
+    if (st != FT_OK) return st;
+    if (!gradB) return fail(nullptr, FT_EINVAL, "gradB is NULL");
+    const bool sparse = uniq_rows && uniq_grad && n_uniq_dev;
+    if ((uniq_rows || uniq_grad || n_uniq_dev) && !sparse)
+        return fail(nullptr, FT_EINVAL,
+                    "the sparse form needs uniq_rows, uniq_grad and n_uniq_dev");
+    for (int n = 0; n < p->order; ++n) {
+        if (!gradB[n]) return fail(nullptr, FT_EINVAL, "gradB[%d] is NULL", n);
+        if (gradA && !gradA[n])
+            return fail(nullptr, FT_EINVAL, "gradA[%d] is NULL", n);
+        if (sparse && (!uniq_rows[n] || !uniq_grad[n]))
+            return fail(nullptr, FT_EINVAL, "uniq_rows/grad[%d] is NULL", n);
+    }
+    hipStream_t s = (hipStream_t)hip_stream;
+    const MbLayout L = mb_layout(p, m);
+    const int N = p->order;
+    const float *Bp[kMaxOrder] = {};
+    st = pad_cores(p, L, B, workspace, s, Bp);
+    if (st != FT_OK) return st;
+
+    // per-sample row gradients (c, d recomputed)
+    FactorArgs fa{};
+    for (int n = 0; n < N; ++n) {
+        fa.idx[n] = idx[n];
+        fa.A[n] = A[n];
+        fa.B[n] = Bp[n];
+    }
+    fa.val = val;
+    fa.m = (int32_t)m;
+    fa.G = at<float>(workspace, L.G);
+    fa.loss_part = at<double>(workspace, L.dpart);
+    int nb = 0;
+    HIPCHK0(launch_factor_grad(L.sh, fa, &nb, s));
+
+    // sort the minibatch's rows per mode (one segment)
+    SortPass sp{};
+    sp.N = N;
+    sp.nnz = m;
+    sp.M = m;
+    sp.nseg = 1;
+    sp.tiles_per_seg = L.tps;
+    sp.counts = at<uint32_t>(workspace, L.counts);
+    uint32_t *sk[2] = {at<uint32_t>(workspace, L.sk0),
+                       at<uint32_t>(workspace, L.sk1)};
+    uint32_t *sv[2] = {at<uint32_t>(workspace, L.sv0),
+                       at<uint32_t>(workspace, L.sv1)};
+    int64_t maxrow = 0;
+    for (int n = 0; n < N; ++n) maxrow = std::max<int64_t>(maxrow, p->dims[n] - 1);
+    int bits = 0;
+    while ((1ll << bits) <= maxrow) ++bits;
+    const int passes = bits == 0 ? 1 : (bits + 7) / 8;
+    int cur = 0;
+    for (int pass = 0; pass < passes; ++pass) {
+        sp.shift = 8 * pass;
+        const int out = pass == 0 ? 0 : cur ^ 1;
+        for (int n = 0; n < N; ++n) {
+            sp.key_in[n] = pass == 0 ? reinterpret_cast<const uint32_t *>(idx[n])
+                                     : sk[cur] + (size_t)n * m;
+            sp.val_in[n] = pass == 0 ? nullptr : sv[cur] + (size_t)n * m;
+            sp.key_out[n] = sk[out] + (size_t)n * m;
+            sp.val_out[n] = sv[out] + (size_t)n * m;
+        }
+        HIPCHK0(launch_sort_pass(sp, s));
+        cur = out;
+    }
+
+    SegArgs sa{};
+    sa.N = N;
+    sa.J4 = L.sh.J4;
+    sa.m = (int32_t)m;
+    sa.nchunks = L.nch;
+    sa.G = fa.G;
+    sa.first = at<float>(workspace, L.first);
+    sa.last = at<float>(workspace, L.last);
+    sa.apply = 2;
+    sa.scale = grad_out_dev;
+    for (int n = 0; n < N; ++n) {
+        sa.rows[n] = sk[cur] + (size_t)n * m;
+        sa.pos[n] = sv[cur] + (size_t)n * m;
+        sa.A[n] = const_cast<float *>(A[n]);
+        sa.grad[n] = gradA ? gradA[n] : nullptr;
+        if (gradA)
+            HIPCHK0(launch_fill_zero(gradA[n], p->dims[n] * L.sh.J4, s));
+    }
+    if (sparse) {
+        UniqueScan u{};
+        u.N = N;
+        u.m = (int32_t)m;
+        u.ntiles = L.ntiles_scan;
+        u.tile_count = at<uint32_t>(workspace, L.tile_count);
+        u.total = n_uniq_dev;
+        for (int n = 0; n < N; ++n) {
+            u.rows[n] = sa.rows[n];
+            u.ordinal[n] = at<uint32_t>(workspace, L.ordinal) + (size_t)n * m;
+            sa.ordinal[n] = u.ordinal[n];
+            sa.uniq_rows[n] = uniq_rows[n];
+            sa.uniq_grad[n] = uniq_grad[n];
+        }
+        HIPCHK0(launch_unique_scan(u, s));
+    }
+    HIPCHK0(launch_seg_reduce(sa, s));
+    HIPCHK0(launch_seg_fixup(sa, s));
+
+    // core gradients over the minibatch
+    CoreArgs ca{};
+    for (int n = 0; n < N; ++n) {
+        ca.idx[n] = idx[n];
+        ca.A[n] = A[n];
+        ca.B[n] = Bp[n];
+    }
+    ca.val = val;
+    ca.count = m;
+    ca.part = at<float>(workspace, L.core_part);
+    ca.loss_part = at<double>(workspace, L.dpart);
+    HIPCHK0(launch_core_grad(L.sh, ca, L.nb_core, s));
+    CoreUpdateArgs ua{};
+    ua.part = ca.part;
+    ua.nblocks = L.nb_core;
+    ua.apply = 0;
+    ua.R = p->R;
+    ua.scale = grad_out_dev;
+    for (int n = 0; n < N; ++n) {
+        ua.gout[n] = gradB[n];
+        ua.Jn[n] = p->J[n];
+    }
+    HIPCHK0(launch_core_update(L.sh, ua, s));
     return FT_OK;
 }

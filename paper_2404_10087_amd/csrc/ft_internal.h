@@ -69,6 +69,17 @@ hipError_t launch_factor_grad(const Shape &sh, const FactorArgs &a, int *nblocks
                               hipStream_t s);
 int factor_grad_blocks(int32_t m);
 
+struct HogArgs {
+    const int32_t *idx[kMaxOrder];   // epoch-order coordinates
+    const float *val;
+    int64_t count;
+    float *A[kMaxOrder];
+    const float *B[kMaxOrder];
+    float lr, lam;
+    double *tile_loss;               // [ceil(count / 16)]
+};
+hipError_t launch_hogwild(const Shape &sh, const HogArgs &a, hipStream_t s);
+
 struct SegArgs {
     int N;
     int J4;
@@ -82,9 +93,17 @@ struct SegArgs {
     float *last;                      // [N][nchunks][J4]
     float lr, lam;
     int mean;                         // FT_ROW_MEAN
-    int apply;                        // 1: update A; 0: write grad/count
-    float *grad[kMaxOrder];           // dense I_n x J4 (apply == 0)
+    int apply;                        // 1: update A; 0: write grad/count;
+                                      // 2: autograd outputs (no lambda term)
+    float *grad[kMaxOrder];           // dense I_n x J4 (apply 0, 2; may be
+                                      // null in mode 2)
     int32_t *count[kMaxOrder];        // I_n (apply == 0)
+    // apply == 2: compacted sparse rows, scaled by *scale (null: 1)
+    const uint32_t *ordinal[kMaxOrder];  // unique-row index of each sorted
+                                         // element (segment starts only read)
+    int32_t *uniq_rows[kMaxOrder];       // [#unique] or null
+    float *uniq_grad[kMaxOrder];         // [#unique][J4] or null
+    const float *scale;
 };
 hipError_t launch_seg_reduce(const SegArgs &a, hipStream_t s);
 hipError_t launch_seg_fixup(const SegArgs &a, hipStream_t s);
@@ -114,9 +133,32 @@ struct CoreUpdateArgs {
     double inv_count;     // 1 / |Omega| (or 1 / minibatch size)
     float lr, lam;
     int apply;
+    // unpadded per-mode output (J_n x R row-major), scaled by *scale
+    float *gout[kMaxOrder];
+    int Jn[kMaxOrder];
+    int R;
+    const float *scale;
 };
 hipError_t launch_core_update(const Shape &sh, const CoreUpdateArgs &a,
                               hipStream_t s);
+
+// ---------------------------------------------------------------- autograd
+// dst (J4 x R16, zero padded) <- src (J x R dense row-major)
+hipError_t launch_pad_matrix(const float *src, int J, int R, float *dst,
+                             int J4, int R16, hipStream_t s);
+// Unique-row ordinals of a sorted row array per mode: ordinal[i] = number of
+// segment heads before i; total[n] = number of unique rows (int64).
+struct UniqueScan {
+    int N;
+    int32_t m;
+    int ntiles;
+    const uint32_t *rows[kMaxOrder];
+    uint32_t *ordinal[kMaxOrder];
+    uint32_t *tile_count;   // [N][ntiles]
+    int64_t *total;         // [N]
+};
+hipError_t launch_unique_scan(const UniqueScan &u, hipStream_t s);
+hipError_t launch_fill_zero(float *p, int64_t n, hipStream_t s);
 
 // ---------------------------------------------------------------- evaluation
 struct EvalArgs {
@@ -126,6 +168,7 @@ struct EvalArgs {
     const float *A[kMaxOrder];
     const float *B[kMaxOrder];
     double *part;         // [nblocks][2]: sum r^2, sum |r|
+    int half_square;      // 1: first sum is sum r^2 / 2
 };
 int eval_blocks(int64_t count);
 hipError_t launch_eval(const Shape &sh, const EvalArgs &a, int nblocks,

@@ -214,8 +214,11 @@ __global__ __launch_bounds__(256) void core_update_kernel(CoreUpdateArgs a,
     if (sl == 0 && e < E) {
         const float g = ((part[0][el] + part[1][el]) + part[2][el]) + part[3][el];
         if (a.grad_out) a.grad_out[e] = g;
+        const int n = e / (J4 * R16);
+        const int j = (e / R16) % J4, r = e % R16;
+        if (a.gout[n] && j < a.Jn[n] && r < a.R)
+            a.gout[n][j * a.R + r] = g * (a.scale ? *a.scale : 1.f);
         if (a.apply) {
-            const int n = e / (J4 * R16);
             float *bp = a.B[n] + (e - n * J4 * R16);
             const float bv = *bp;
             *bp = bv - a.lr * (float)((double)g * a.inv_count + (double)a.lam * bv);

@@ -59,7 +59,7 @@ __global__ __launch_bounds__(256) void eval_kernel(EvalArgs a, int64_t ntiles) {
         xh = sum_quads(xh);
         if (valid && q == 0) {
             const double r = (double)(xh - a.val[ps]);
-            sse += r * r;
+            sse += a.half_square ? 0.5 * r * r : r * r;
             sae += fabs(r);
         }
     }

@@ -36,53 +36,56 @@ int factor_grad_blocks(int32_t m) {
     return blocks < 1 ? 1 : blocks;
 }
 
+// Per-wave state and arithmetic of one 16-sample tile (shared by the
+// deterministic and the Hogwild factor kernels).
 template <int N, int KQ, int RB>
-__global__ __launch_bounds__(kFactorThreads) void factor_grad_kernel(
-    FactorArgs a, int ntiles) {
-    constexpr int J4 = 4 * KQ;
-    constexpr int R16 = 16 * RB;
-    constexpr int JB = (KQ + 3) / 4;   // 16-row output blocks of J4
-    const int lane = threadIdx.x & 63, q = lane >> 4, c = lane & 15;
-
-    // A-operands: B^(n)T for the contraction over j, B^(n) for the one over r.
+struct FactorTile {
+    static constexpr int J4 = 4 * KQ;
+    static constexpr int R16 = 16 * RB;
+    static constexpr int JB = (KQ + 3) / 4;   // 16-row output blocks of J4
+    int q, c;
+    // A-operands: B^(n)T for the contraction over j, B^(n) for the one over r
     float bf[N][RB][KQ];
     float bb[N][JB][RB][4];
+    floatx4 D[N][RB];
+
+    __device__ __forceinline__ void load_B(const float *const *Bm) {
+        const int lane = threadIdx.x & 63;
+        q = lane >> 4;
+        c = lane & 15;
 #pragma unroll
-    for (int n = 0; n < N; ++n) {
-        const float *B = a.B[n];
-#pragma unroll
-        for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-            for (int t = 0; t < KQ; ++t)
-                bf[n][rb][t] = B[(KQ * q + t) * R16 + 16 * rb + c];
-#pragma unroll
-        for (int jb = 0; jb < JB; ++jb) {
-            const int j = 16 * jb + c;
+        for (int n = 0; n < N; ++n) {
+            const float *B = Bm[n];
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-                for (int v = 0; v < 4; ++v)
-                    bb[n][jb][rb][v] =
-                        j < J4 ? B[j * R16 + 16 * rb + 4 * q + v] : 0.f;
+                for (int t = 0; t < KQ; ++t)
+                    bf[n][rb][t] = B[(KQ * q + t) * R16 + 16 * rb + c];
+#pragma unroll
+            for (int jb = 0; jb < JB; ++jb) {
+                const int j = 16 * jb + c;
+#pragma unroll
+                for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v)
+                        bb[n][jb][rb][v] =
+                            j < J4 ? B[j * R16 + 16 * rb + 4 * q + v] : 0.f;
+            }
         }
     }
 
-    double loss = 0.0;
-    const int nwaves = gridDim.x * (kFactorThreads / 64);
-    for (int tile = blockIdx.x * (kFactorThreads / 64) + (threadIdx.x >> 6);
-         tile < ntiles; tile += nwaves) {
-        const int p = tile * 16 + c;
-        const bool valid = p < a.m;
-        const int ps = valid ? p : a.m - 1;
-
+    // Sample ps (this lane's column): gather its rows, C^(n)T on the matrix
+    // cores, D^(n) by prefix/suffix products; returns xhat (all four lanes of
+    // the column hold it).
+    __device__ __forceinline__ float forward(const int32_t *const *idx,
+                                             const float *const *A, int64_t ps,
+                                             int *rows) {
         float arow[N][KQ];
 #pragma unroll
         for (int n = 0; n < N; ++n) {
-            const int row = a.idx[n][ps];
-            load_row_part<KQ>(a.A[n] + (int64_t)row * J4 + KQ * q, arow[n]);
+            rows[n] = idx[n][ps];
+            load_row_part<KQ>(A[n] + (int64_t)rows[n] * J4 + KQ * q, arow[n]);
         }
-        const float x = a.val[ps];
-
         floatx4 C[N][RB];
 #pragma unroll
         for (int n = 0; n < N; ++n)
@@ -94,8 +97,6 @@ __global__ __launch_bounds__(kFactorThreads) void factor_grad_kernel(
                     acc = mfma_16x16x4(bf[n][rb][t], arow[n][t], acc);
                 C[n][rb] = acc;
             }
-
-        floatx4 D[N][RB];
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb) {
             floatx4 pre = {1.f, 1.f, 1.f, 1.f};
@@ -111,36 +112,98 @@ __global__ __launch_bounds__(kFactorThreads) void factor_grad_kernel(
                 suf *= C[n][rb];
             }
         }
-
         float xh = 0.f;
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
             for (int v = 0; v < 4; ++v) xh += C[0][rb][v] * D[0][rb][v];
-        xh = sum_quads(xh);
-        const float r = valid ? xh - x : 0.f;
-        if (valid && q == 0) loss += 0.5 * (double)r * (double)r;
+        return sum_quads(xh);
+    }
 
+    // Rows 16 jb + 4q .. +3 of g^(n) = r * B^(n) d^(n) for this lane's sample.
+    __device__ __forceinline__ floatx4 grad(int n, int jb, float r) const {
+        floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                acc = mfma_16x16x4(bb[n][jb][rb][v], r * D[n][rb][v], acc);
+        return acc;
+    }
+};
+
+template <int N, int KQ, int RB>
+__global__ __launch_bounds__(kFactorThreads) void factor_grad_kernel(
+    FactorArgs a, int ntiles) {
+    using T = FactorTile<N, KQ, RB>;
+    T tl;
+    tl.load_B(a.B);
+    double loss = 0.0;
+    const int nwaves = gridDim.x * (kFactorThreads / 64);
+    for (int tile = blockIdx.x * (kFactorThreads / 64) + (threadIdx.x >> 6);
+         tile < ntiles; tile += nwaves) {
+        const int p = tile * 16 + tl.c;
+        const bool valid = p < a.m;
+        const int ps = valid ? p : a.m - 1;
+        int rows[N];
+        const float xh = tl.forward(a.idx, a.A, ps, rows);
+        const float r = valid ? xh - a.val[ps] : 0.f;
+        if (valid && tl.q == 0) loss += 0.5 * (double)r * (double)r;
 #pragma unroll
         for (int n = 0; n < N; ++n) {
-            float *Gn = a.G + ((int64_t)n * a.m + p) * J4;
+            float *Gn = a.G + ((int64_t)n * a.m + p) * T::J4;
 #pragma unroll
-            for (int jb = 0; jb < JB; ++jb) {
-                floatx4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-                    for (int v = 0; v < 4; ++v)
-                        acc = mfma_16x16x4(bb[n][jb][rb][v],
-                                           r * D[n][rb][v], acc);
-                const int j0 = 16 * jb + 4 * q;
-                if (valid && j0 < J4)
-                    *reinterpret_cast<floatx4 *>(Gn + j0) = acc;
+            for (int jb = 0; jb < T::JB; ++jb) {
+                const floatx4 g = tl.grad(n, jb, r);
+                const int j0 = 16 * jb + 4 * tl.q;
+                if (valid && j0 < T::J4)
+                    *reinterpret_cast<floatx4 *>(Gn + j0) = g;
             }
         }
     }
     const double tot = block_sum_256(loss);
     if (threadIdx.x == 0) a.loss_part[blockIdx.x] = tot;
+}
+
+// Hogwild fast mode (the paper's execution model, Algorithm 4): persistent
+// waves sweep all 16-sample tiles of the epoch order with no minibatch
+// barrier; each tile reads its rows, forms g, and applies
+// a <- a - lr_A (g + lambda_A a) at once with hardware float atomics, so
+// concurrent tiles race on shared rows by design. One FP64 loss per tile.
+template <int N, int KQ, int RB>
+__global__ __launch_bounds__(kFactorThreads) void hogwild_kernel(HogArgs a) {
+    using T = FactorTile<N, KQ, RB>;
+    T tl;
+    tl.load_B(a.B);
+    const int64_t ntiles = (a.count + 15) / 16;
+    const int64_t nwaves = (int64_t)gridDim.x * (kFactorThreads / 64);
+    for (int64_t tile = (int64_t)blockIdx.x * (kFactorThreads / 64) +
+                        (threadIdx.x >> 6);
+         tile < ntiles; tile += nwaves) {
+        const int64_t p = tile * 16 + tl.c;
+        const bool valid = p < a.count;
+        const int64_t ps = valid ? p : a.count - 1;
+        int rows[N];
+        const float xh = tl.forward(a.idx, a.A, ps, rows);
+        const float r = valid ? xh - a.val[ps] : 0.f;
+        double tl_loss = (valid && tl.q == 0) ? 0.5 * (double)r * (double)r : 0.0;
+        tl_loss = wave_sum(tl_loss);
+        if ((threadIdx.x & 63) == 0) a.tile_loss[tile] = tl_loss;
+#pragma unroll
+        for (int n = 0; n < N; ++n) {
+#pragma unroll
+            for (int jb = 0; jb < T::JB; ++jb) {
+                const floatx4 g = tl.grad(n, jb, r);
+                const int j0 = 16 * jb + 4 * tl.q;
+                if (valid && j0 < T::J4) {
+                    float *ap = a.A[n] + (int64_t)rows[n] * T::J4 + j0;
+#pragma unroll
+                    for (int v = 0; v < 4; ++v)
+                        unsafeAtomicAdd(ap + v, -a.lr * (g[v] + a.lam * ap[v]));
+                }
+            }
+        }
+    }
 }
 
 template <int N, int KQ, int RB>
@@ -187,11 +250,70 @@ hipError_t launch_factor_grad(const Shape &sh, const FactorArgs &a, int *nblocks
     return hipErrorInvalidValue;
 }
 
+template <int N, int KQ, int RB>
+static hipError_t launch_hw(const HogArgs &a, int blocks, hipStream_t s) {
+    hipLaunchKernelGGL((hogwild_kernel<N, KQ, RB>), dim3(blocks),
+                       dim3(kFactorThreads), 0, s, a);
+    return hipGetLastError();
+}
+
+template <int N, int KQ>
+static hipError_t launch_hw_r(const Shape &sh, const HogArgs &a, int blocks,
+                              hipStream_t s) {
+    return sh.R16 == 16 ? launch_hw<N, KQ, 1>(a, blocks, s)
+                        : launch_hw<N, KQ, 2>(a, blocks, s);
+}
+
+template <int N>
+static hipError_t launch_hw_j(const Shape &sh, const HogArgs &a, int blocks,
+                              hipStream_t s) {
+    switch (sh.J4) {
+    case 4: return launch_hw_r<N, 1>(sh, a, blocks, s);
+    case 8: return launch_hw_r<N, 2>(sh, a, blocks, s);
+    case 12: return launch_hw_r<N, 3>(sh, a, blocks, s);
+    case 16: return launch_hw_r<N, 4>(sh, a, blocks, s);
+    case 20: return launch_hw_r<N, 5>(sh, a, blocks, s);
+    case 24: return launch_hw_r<N, 6>(sh, a, blocks, s);
+    case 28: return launch_hw_r<N, 7>(sh, a, blocks, s);
+    case 32: return launch_hw_r<N, 8>(sh, a, blocks, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+int hogwild_blocks(int64_t count) {
+    int64_t ntiles = (count + 15) / 16;
+    int64_t blocks = (ntiles + 3) / 4;
+    if (blocks > kFactorMaxBlocks) blocks = kFactorMaxBlocks;
+    return blocks < 1 ? 1 : (int)blocks;
+}
+
+hipError_t launch_hogwild(const Shape &sh, const HogArgs &a, hipStream_t s) {
+    const int blocks = hogwild_blocks(a.count);
+    switch (sh.N) {
+    case 2: return launch_hw_j<2>(sh, a, blocks, s);
+    case 3: return launch_hw_j<3>(sh, a, blocks, s);
+    case 4: return launch_hw_j<4>(sh, a, blocks, s);
+    case 5: return launch_hw_j<5>(sh, a, blocks, s);
+    }
+    return hipErrorInvalidValue;
+}
+
 // ------------------------------------------------------------ row reduction
 __device__ __forceinline__ void finish_row(const SegArgs &a, int n, int j,
                                            bool col, uint32_t row, float sum,
-                                           int cnt) {
+                                           int cnt, int start) {
     if (!col) return;
+    if (a.apply == 2) {
+        // autograd: gradient of the data term only, times grad_out
+        const float g = sum * (a.scale ? *a.scale : 1.f);
+        if (a.grad[n]) a.grad[n][(int64_t)row * a.J4 + j] = g;
+        if (a.uniq_grad[n]) {
+            const uint32_t ord = a.ordinal[n][start];
+            a.uniq_grad[n][(int64_t)ord * a.J4 + j] = g;
+            if (j == 0 && a.uniq_rows[n]) a.uniq_rows[n][ord] = (int32_t)row;
+        }
+        return;
+    }
     float *ap = a.A[n] + (int64_t)row * a.J4 + j;
     const float av = *ap;
     float g = sum + (float)cnt * a.lam * av;
@@ -224,6 +346,7 @@ __global__ __launch_bounds__(256) void seg_reduce_kernel(SegArgs a) {
 
     float acc = 0.f;
     int cnt = 0;
+    int start = i0;
     uint32_t cur = first_row;
     bool is_first = true;
     for (int base = i0; base < i1; base += 8) {
@@ -244,10 +367,11 @@ __global__ __launch_bounds__(256) void seg_reduce_kernel(SegArgs a) {
                 if (is_first && starts_before) {
                     if (col) *first = acc;
                 } else {
-                    finish_row(a, n, j, col, cur, acc, cnt);
+                    finish_row(a, n, j, col, cur, acc, cnt, start);
                 }
                 acc = 0.f;
                 cnt = 0;
+                start = base + u;
                 cur = rr[u];
                 is_first = false;
             }
@@ -257,7 +381,7 @@ __global__ __launch_bounds__(256) void seg_reduce_kernel(SegArgs a) {
     }
     const bool span_before = is_first && starts_before;
     if (!span_before && !continues_after) {
-        finish_row(a, n, j, col, cur, acc, cnt);
+        finish_row(a, n, j, col, cur, acc, cnt, start);
     } else if (col) {
         if (is_first) *first = acc;
         *last = acc;
@@ -292,7 +416,7 @@ __global__ __launch_bounds__(256) void seg_fixup_kernel(SegArgs a, int LP) {
     const float *last = a.last + (int64_t)n * a.nchunks * a.J4 + j;
     float acc = last[(int64_t)c0 * a.J4];
     for (int cc = c0 + 1; cc <= c; ++cc) acc += first[(int64_t)cc * a.J4];
-    finish_row(a, n, j, col, row, acc, end - start);
+    finish_row(a, n, j, col, row, acc, end - start, start);
 }
 
 static int lanes_per_group(int J4) {

@@ -1,0 +1,180 @@
+"""The torch.autograd.Function over ft_mb_forward / ft_mb_backward against
+FP64 finite differences and the oracle's gradients; a torch Adam loop on top
+of it against the same Adam driven by oracle gradients."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from paper_2404_10087_amd.autograd import FastTuckerModel
+from tests.gpu_util import f64, rel_norm
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+GRAD_RTOL = 1e-5
+
+
+def model_and_batch(w, T, A0, B0, idx=None, val=None):
+    model = FastTuckerModel(w.dims, w.J, w.R, A0, B0, device=DEV)
+    idx = T.train_idx if idx is None else idx
+    val = T.train_val if val is None else val
+    ti = torch.as_tensor(np.ascontiguousarray(idx), device=DEV)
+    tv = torch.as_tensor(np.ascontiguousarray(val, dtype=np.float32),
+                         device=DEV)
+    return model, ti, tv
+
+
+def grads(model):
+    gA = [a.grad.to_dense()[:, :j].cpu().numpy()
+          for a, j in zip(model.A, model.J)]
+    gB = [b.grad.cpu().numpy() for b in model.B]
+    return gA, gB
+
+
+def test_backward_matches_fp64_finite_differences():
+    w = synth.get("c4")
+    T = synth.make_tensor(w)
+    A0, B0 = synth.init_params(w.init_seed, w.dims, w.J, w.R, 0.5)
+    model, ti, tv = model_and_batch(w, T, A0, B0)
+    loss = model.loss(ti, tv)
+    loss.backward()
+    gA, gB = grads(model)
+    A, B = f64(A0), f64(B0)
+    idx, vals = T.train_idx, T.train_val.astype(np.float64)
+
+    def f():
+        return 0.5 * np.sum((oracle.predict(A, B, idx) - vals) ** 2)
+
+    assert loss.item() == pytest.approx(f(), rel=1e-5)
+    for mats, got in ((A, gA), (B, gB)):
+        for n in range(3):
+            fd = np.zeros_like(mats[n])
+            for k in np.ndindex(*mats[n].shape):
+                w0 = mats[n][k]
+                h = 1e-6 * max(1.0, abs(w0))
+                mats[n][k] = w0 + h
+                fp = f()
+                mats[n][k] = w0 - h
+                fm = f()
+                mats[n][k] = w0
+                fd[k] = (fp - fm) / (2 * h)
+            assert rel_norm([got[n]], [fd]) < GRAD_RTOL, n
+
+
+@pytest.mark.parametrize("J,R,dims,m", [(4, 4, (100, 100, 100), 9000),
+                                        (16, 16, (300, 200, 50), 20000),
+                                        (3, 5, (40, 30, 20, 10), 3000)])
+def test_backward_matches_oracle_gradients_dense_and_sparse(J, R, dims, m):
+    w = synth.get("c0", dims=dims, nnz=int(m / 0.9) + 1, J=J, R=R,
+                  index_dist="zipf", zipf_s=1.1)
+    T = synth.make_tensor(w)
+    A0, B0 = synth.init_params(5, w.dims, J, R, 0.4)
+    _, OG, OK = oracle.factor_minibatch(f64(A0), f64(B0), T.train_idx,
+                                        T.train_val.astype(np.float64), 0.0,
+                                        0.0, False, apply=False, want_grad=True)
+    oloss, OGB = oracle.core_grad(f64(A0), f64(B0), T.train_idx,
+                                  T.train_val.astype(np.float64))
+    for sparse in (False, True):
+        model, ti, tv = model_and_batch(w, T, A0, B0)
+        loss = model.loss(ti, tv, sparse=sparse)
+        (2.5 * loss).backward()
+        assert loss.item() == pytest.approx(oloss, rel=1e-5)
+        gA, gB = grads(model)
+        for n in range(w.order):
+            assert rel_norm([gA[n]], [2.5 * OG[n]]) < GRAD_RTOL, (sparse, n)
+            assert rel_norm([gB[n]], [2.5 * OGB[n]]) < GRAD_RTOL, (sparse, n)
+            if sparse:
+                g = model.A[n].grad
+                assert g.is_sparse
+                rows = g._indices()[0].cpu().numpy()
+                np.testing.assert_array_equal(rows, np.flatnonzero(OK[n]))
+
+
+def test_backward_is_bitwise_reproducible():
+    w = synth.get("c0", dims=(300, 200, 50), nnz=30000, J=16, R=16,
+                  index_dist="zipf", zipf_s=1.2)
+    T = synth.make_tensor(w)
+    A0, B0 = synth.init_params(5, w.dims, 16, 16, 0.4)
+    out = []
+    for _ in range(2):
+        model, ti, tv = model_and_batch(w, T, A0, B0)
+        model.loss(ti, tv).backward()
+        out.append(grads(model))
+    for x, y in zip(out[0][0] + out[0][1], out[1][0] + out[1][1]):
+        np.testing.assert_array_equal(x, y)
+
+
+def test_adam_on_the_function_tracks_oracle_driven_adam():
+    """Ten epochs of torch Adam (minibatches of 512 in a seeded order) on the
+    device, against the same optimiser on FP64 CPU parameters whose
+    gradients come from the oracle."""
+    w = synth.get("c0")
+    T = synth.make_tensor(w)
+    A0, B0 = synth.init_params(w.init_seed, w.dims, w.J, w.R, 0.5)
+    model, ti, tv = model_and_batch(w, T, A0, B0)
+    opt = torch.optim.Adam(list(model.A) + list(model.B), lr=1e-2)
+    Ac = [torch.tensor(a, dtype=torch.float64, requires_grad=True) for a in A0]
+    Bc = [torch.tensor(b, dtype=torch.float64, requires_grad=True) for b in B0]
+    optc = torch.optim.Adam(Ac + Bc, lr=1e-2)
+    nnz = T.train_idx.shape[1]
+    tvals = T.train_val.astype(np.float64)
+    first = last = None
+    for ep in range(10):
+        p = synth.epoch_perm(w.order_seed, ep, nnz)
+        for lo in range(0, nnz, w.M):
+            s = p[lo:lo + w.M]
+            opt.zero_grad()
+            l = model.loss(ti[:, s].contiguous(), tv[s].contiguous())
+            l.backward()
+            opt.step()
+            idx = np.ascontiguousarray(T.train_idx[:, s])
+            An = [a.detach().numpy().copy() for a in Ac]
+            Bn = [b.detach().numpy().copy() for b in Bc]
+            ol, OG, _ = oracle.factor_minibatch(An, Bn, idx, tvals[s], 0.0,
+                                                0.0, False, apply=False,
+                                                want_grad=True)
+            _, OGB = oracle.core_grad(An, Bn, idx, tvals[s])
+            for n in range(3):
+                Ac[n].grad = torch.as_tensor(OG[n])
+                Bc[n].grad = torch.as_tensor(OGB[n])
+            optc.step()
+            if first is None:
+                first = (l.item(), ol)
+            last = (l.item(), ol)
+    assert first[0] == pytest.approx(first[1], rel=1e-5)
+    assert last[1] < 0.5 * first[1]
+    A1 = [a.detach()[:, :w.J].cpu().numpy() for a in model.A]
+    B1 = [b.detach().cpu().numpy() for b in model.B]
+    osse, _ = oracle.residual_stats([a.detach().numpy() for a in Ac],
+                                    [b.detach().numpy() for b in Bc],
+                                    T.test_idx, T.test_val.astype(np.float64))
+    gsse, _ = oracle.residual_stats(f64(A1), f64(B1), T.test_idx,
+                                    T.test_val.astype(np.float64))
+    assert np.sqrt(gsse) == pytest.approx(np.sqrt(osse), rel=1e-2)
+
+
+def test_full_size_one_million_sample_minibatch():
+    """The differentiation workload: c1's tensor with J = R = 32, the loss of
+    one 1,000,000-nonzero minibatch; forward and backward against the
+    oracle (the sparse row form and the core gradients)."""
+    w1 = synth.get("c1")
+    T = synth.make_tensor(w1)
+    J = R = 32
+    s = slice(0, 1_000_000)
+    idx = np.ascontiguousarray(T.train_idx[:, s])
+    val = T.train_val[s]
+    A0, B0 = synth.init_params(2004, w1.dims, J, R, 0.25)
+    w = synth.get("c1", J=J, R=R)
+    model, ti, tv = model_and_batch(w, T, A0, B0, idx, val)
+    loss = model.loss(ti, tv, sparse=True)
+    loss.backward()
+    oloss, OG, OK = oracle.factor_minibatch(f64(A0), f64(B0), idx,
+                                            val.astype(np.float64), 0.0, 0.0,
+                                            False, apply=False, want_grad=True)
+    _, OGB = oracle.core_grad(f64(A0), f64(B0), idx, val.astype(np.float64))
+    assert loss.item() == pytest.approx(oloss, rel=1e-5)
+    gA, gB = grads(model)
+    for n in range(3):
+        assert rel_norm([gA[n]], [OG[n]]) < GRAD_RTOL, n
+        assert rel_norm([gB[n]], [OGB[n]]) < GRAD_RTOL, n

@@ -317,3 +317,38 @@ def test_unequal_ranks_per_mode():
                               T.train_val.astype(np.float64))
     for n in range(3):
         assert rel_norm([CG[n]], [OCG[n]]) < GRAD_RTOL
+
+
+# ----------------------------------------------------------------- fast mode
+@pytest.mark.parametrize("name,tol", [("c0", 0.02), ("zipf", 0.05)])
+def test_hogwild_fast_mode_tracks_sequential_tiles(name, tol):
+    """The fast mode applies per-sample steps from concurrent 16-sample tiles
+    with float atomics (no determinism). Its trajectory must stay close to the
+    oracle's sequential execution of the same tiles (M = 16, summed rows) on
+    the same order: test RMSE after three alternating epochs within tol."""
+    w = W[name]
+    ft, T, A0, B0 = setup(w)
+    ft.set_options(deterministic=0, row_scale=0)
+    A, B = f64(A0), f64(B0)
+    tv = T.train_val.astype(np.float64)
+    sv = T.test_val.astype(np.float64)
+    for ep in range(3):
+        p = perm_for(w, T, ep)
+        ft.set_epoch_order(p)
+        mb = ft.epoch_factors()
+        assert mb.shape == (ft.num_minibatches(),) and np.all(np.isfinite(mb))
+        oracle.factor_epoch(A, B, T.train_idx, tv, p, 16, w.lr_A, w.lam_A,
+                            False)
+        ft.epoch_core()
+        oracle.core_epoch(A, B, T.train_idx, tv, w.lr_B, w.lam_B)
+    osse, _ = oracle.residual_stats(A, B, T.test_idx, sv)
+    ormse = np.sqrt(osse / len(sv))
+    assert ft.rmse(FT_TEST) == pytest.approx(ormse, rel=tol)
+
+
+def test_fast_mode_rejects_minibatch_not_multiple_of_tile():
+    w = W["c0"]
+    ft, T, _, _ = setup(w, with_test=False)
+    with pytest.raises(FtError) as e:
+        ft.set_options(deterministic=0, minibatch=500)
+    assert e.value.status == 1

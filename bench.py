@@ -108,7 +108,23 @@ def main():
     ap.add_argument("--config", default="c1")
     ap.add_argument("--cpu-sample", type=int, default=46 * 65536)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cache-dir", default=os.environ.get("FT_SYNTH_CACHE"),
+                    help="reuse the generated tensor across runs")
+    ap.add_argument("--copy-calibration", type=int, default=0,
+                    metavar="MiB", help="only run a plain device copy of this "
+                    "many MiB (known traffic for scaling HBM counters)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        n = args.copy_calibration * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_read": 4 * n,
+                          "copy_calibration_bytes_written": 4 * n}))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the "
               "multi-GPU design is described but not built", file=sys.stderr)
@@ -120,7 +136,7 @@ def main():
 
     w = synth.get(args.config)
     t_gen = time.perf_counter()
-    T = synth.make_tensor(w)
+    T = synth.make_tensor(w, cache_dir=args.cache_dir)
     A0, B0 = synth.init_params(w.init_seed, w.dims, w.J, w.R, w.init_a_std,
                                w.init_b_std, w.init_dist)
     t_gen = time.perf_counter() - t_gen

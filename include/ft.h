@@ -45,7 +45,11 @@ typedef enum {
 typedef enum { FT_TRAIN = 0, FT_TEST = 1 } ft_set;
 
 /* Arithmetic of the a.B contraction (the rest of the path is FP32; losses and
- * RMSE are reduced in FP64). */
+ * RMSE are reduced in FP64). FT_BF16: factor rows are gathered from a BF16
+ * shadow of A (refreshed whenever a row is updated or set), multiplied with
+ * a BF16 copy of B on the matrix cores and accumulated in FP32; A and B stay
+ * FP32 masters and every update is FP32. FT_BF16 needs the verify mode.
+ * FT_FP8_E4M3 is declared for the format but not available (FT_EINVAL). */
 typedef enum { FT_FP32 = 0, FT_BF16 = 1, FT_FP8_E4M3 = 2 } ft_precision;
 
 /* How a minibatch's summed row gradient is applied (Eq. (12) applied per

@@ -40,6 +40,7 @@ struct ft_handle {
 
     float *A[kMaxOrder] = {};
     float *B[kMaxOrder] = {};
+    uint16_t *A16[kMaxOrder] = {};   // BF16 shadow (precision FT_BF16)
 
     int64_t nnz[2] = {0, 0};
     int32_t *idx[2][kMaxOrder] = {};
@@ -218,6 +219,7 @@ static void release(ft_handle *h) {
     for (int n = 0; n < kMaxOrder; ++n) {
         dfree(h->A[n]);
         dfree(h->B[n]);
+        dfree(h->A16[n]);
         for (int s = 0; s < 2; ++s) {
             dfree(h->idx[s][n]);
             dfree(h->sk[s][n]);
@@ -277,10 +279,13 @@ static ft_status check_options(ft_handle *h, const ft_options *o) {
         if (!std::isfinite(x) || x < 0)
             return fail(h, FT_EINVAL,
                         "learning rates and lambdas must be finite and >= 0");
-    if (o->precision != FT_FP32)
+    if (o->precision != FT_FP32 && o->precision != FT_BF16)
         return fail(h, FT_EINVAL,
-                    "precision %d is not available in this build (FP32 only)",
+                    "precision %d is not available in this build (FP32, BF16)",
                     o->precision);
+    if (o->precision == FT_BF16 && o->deterministic == 0)
+        return fail(h, FT_EINVAL,
+                    "the BF16 contraction is available in verify mode only");
     if (o->row_scale != FT_ROW_SUM && o->row_scale != FT_ROW_MEAN)
         return fail(h, FT_EINVAL, "row_scale must be FT_ROW_SUM or FT_ROW_MEAN");
     if (o->core_step != FT_CORE_PER_EPOCH &&
@@ -298,10 +303,32 @@ static ft_status check_options(ft_handle *h, const ft_options *o) {
     return FT_OK;
 }
 
+// Refresh the BF16 shadow of A^(n) from the FP32 master.
+static ft_status refresh_shadow(ft_handle *h, int n) {
+    if (!h->sh.bf16) return FT_OK;
+    const int64_t count = h->dims[n] * h->sh.J4;
+    if (!h->A16[n]) HIPCHK(h, hipMalloc(&h->A16[n], sizeof(uint16_t) * count));
+    HIPCHK(h, launch_to_bf16(h->A[n], h->A16[n], count, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    return FT_OK;
+}
+
 extern "C" ft_status ft_set_options(ft_handle *h, const ft_options *o) {
     CHECK_HANDLE(h);
     ft_status st = check_options(h, o);
     if (st != FT_OK) return st;
+    const bool bf = o->precision == FT_BF16;
+    if (bf && !h->sh.bf16) {
+        h->sh.bf16 = true;
+        for (int n = 0; n < h->N; ++n) {
+            st = refresh_shadow(h, n);
+            if (st != FT_OK) {
+                h->sh.bf16 = false;
+                return st;
+            }
+        }
+    }
+    h->sh.bf16 = bf;
     if (o->minibatch != h->opt.minibatch ||
         o->shuffle_seed != h->opt.shuffle_seed ||
         o->reshuffle_each_epoch != h->opt.reshuffle_each_epoch)
@@ -616,6 +643,7 @@ static ft_status run_minibatch(ft_handle *h, int64_t b, int apply,
     for (int n = 0; n < h->N; ++n) {
         fa.idx[n] = h->pidx[n] + off;
         fa.A[n] = h->A[n];
+        fa.A16[n] = h->sh.bf16 ? h->A16[n] : nullptr;
         fa.B[n] = h->B[n];
     }
     fa.val = h->pval + off;
@@ -636,6 +664,7 @@ static ft_status run_minibatch(ft_handle *h, int64_t b, int apply,
         sa.rows[n] = h->sk[h->sort_final][n] + off;
         sa.pos[n] = h->sv[h->sort_final][n] + off;
         sa.A[n] = h->A[n];
+        sa.A16[n] = h->sh.bf16 ? h->A16[n] : nullptr;
         sa.grad[n] = grad ? grad[n] : nullptr;
         sa.count[n] = count ? count[n] : nullptr;
     }
@@ -835,6 +864,7 @@ static ft_status core_pass(ft_handle *h, const int32_t *const *idx,
     for (int n = 0; n < h->N; ++n) {
         ca.idx[n] = idx[n];
         ca.A[n] = h->A[n];
+        ca.A16[n] = h->sh.bf16 ? h->A16[n] : nullptr;
         ca.B[n] = h->B[n];
     }
     ca.val = val;
@@ -943,6 +973,7 @@ extern "C" ft_status ft_eval(ft_handle *h, ft_set which, double *sse,
         for (int n = 0; n < h->N; ++n) {
             ea.idx[n] = h->idx[which][n];
             ea.A[n] = h->A[n];
+            ea.A16[n] = h->sh.bf16 ? h->A16[n] : nullptr;
             ea.B[n] = h->B[n];
         }
         ea.val = h->val[which];
@@ -1020,9 +1051,11 @@ extern "C" ft_status ft_set_params(ft_handle *h, int mode, int which,
     CHECK_HANDLE(h);
     if (mode < 0 || mode >= h->N || (which != 0 && which != 1) || !host_in)
         return fail(h, FT_EINVAL, "bad mode/which/in");
-    if (which == 0)
-        return upload_padded(h, h->A[mode], host_in, h->dims[mode], h->J[mode],
-                             h->sh.J4);
+    if (which == 0) {
+        ft_status st = upload_padded(h, h->A[mode], host_in, h->dims[mode],
+                                     h->J[mode], h->sh.J4);
+        return st == FT_OK ? refresh_shadow(h, mode) : st;
+    }
     return upload_padded(h, h->B[mode], host_in, h->J[mode], h->R, h->sh.R16);
 }
 

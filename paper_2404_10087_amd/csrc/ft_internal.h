@@ -29,7 +29,11 @@ struct Shape {
     int N;
     int J4;
     int R16;
+    bool bf16;   // contraction a.B from the BF16 shadow of A (FP32 accumulate)
 };
+
+hipError_t launch_to_bf16(const float *src, uint16_t *dst, int64_t n,
+                          hipStream_t s);
 
 // ---------------------------------------------------------------- builder
 hipError_t launch_epoch_order(uint32_t *perm, int64_t n, uint64_t key,
@@ -57,6 +61,7 @@ hipError_t launch_sort_pass(const SortPass &p, hipStream_t s);
 
 // ---------------------------------------------------------------- factor phase
 struct FactorArgs {
+    const uint16_t *A16[kMaxOrder];  // BF16 shadow of A (bf16 shapes only)
     const int32_t *idx[kMaxOrder];  // coordinates of the minibatch (m entries)
     const float *val;
     int32_t m;
@@ -70,6 +75,7 @@ hipError_t launch_factor_grad(const Shape &sh, const FactorArgs &a, int *nblocks
 int factor_grad_blocks(int32_t m);
 
 struct HogArgs {
+    const uint16_t *A16[kMaxOrder];  // BF16 shadow of A (bf16 shapes only)
     const int32_t *idx[kMaxOrder];   // epoch-order coordinates
     const float *val;
     int64_t count;
@@ -95,6 +101,7 @@ struct SegArgs {
     int mean;                         // FT_ROW_MEAN
     int apply;                        // 1: update A; 0: write grad/count;
                                       // 2: autograd outputs (no lambda term)
+    uint16_t *A16[kMaxOrder];         // BF16 shadow refreshed on update
     float *grad[kMaxOrder];           // dense I_n x J4 (apply 0, 2; may be
                                       // null in mode 2)
     int32_t *count[kMaxOrder];        // I_n (apply == 0)
@@ -113,6 +120,7 @@ hipError_t launch_sum_blocks(const double *part, int nper, int ngroups,
 
 // ---------------------------------------------------------------- core phase
 struct CoreArgs {
+    const uint16_t *A16[kMaxOrder];  // BF16 shadow of A (bf16 shapes only)
     const int32_t *idx[kMaxOrder];
     const float *val;
     int64_t count;
@@ -162,6 +170,7 @@ hipError_t launch_fill_zero(float *p, int64_t n, hipStream_t s);
 
 // ---------------------------------------------------------------- evaluation
 struct EvalArgs {
+    const uint16_t *A16[kMaxOrder];  // BF16 shadow of A (bf16 shapes only)
     const int32_t *idx[kMaxOrder];
     const float *val;
     int64_t count;

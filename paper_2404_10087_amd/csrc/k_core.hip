@@ -27,7 +27,7 @@ int core_grad_blocks(int64_t count) {
     return blocks < 1 ? 1 : (int)blocks;
 }
 
-template <int N, int KQ, int RB>
+template <int N, int KQ, int RB, bool BF>
 __global__ __launch_bounds__(256) void core_grad_kernel(CoreArgs a,
                                                         int64_t ntiles) {
     constexpr int J4 = 4 * KQ;
@@ -37,14 +37,12 @@ __global__ __launch_bounds__(256) void core_grad_kernel(CoreArgs a,
     const int lane = threadIdx.x & 63, q = lane >> 4, c = lane & 15;
     const int wave = threadIdx.x >> 6;
 
-    float bop[N][RB][KQ];   // B-operand: B[k = KQ*q + t][r = 16*rb + c]
+    ColFrag<KQ, BF> bop[N][RB];   // B-operand: B[k = KQ*q + t][r = 16 rb + c]
 #pragma unroll
     for (int n = 0; n < N; ++n)
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-            for (int t = 0; t < KQ; ++t)
-                bop[n][rb][t] = a.B[n][(KQ * q + t) * R16 + 16 * rb + c];
+            bop[n][rb].load(a.B[n], R16, q, 16 * rb + c);
 
     floatx4 grad[N][JB][RB];
 #pragma unroll
@@ -63,23 +61,19 @@ __global__ __launch_bounds__(256) void core_grad_kernel(CoreArgs a,
         const int64_t last = a.count - 1;
         const int64_t ps = base + c <= last ? base + c : last;
 
-        float arow[N][KQ];
+        RowFrag<KQ, BF> arow[N];
 #pragma unroll
         for (int n = 0; n < N; ++n) {
             const int row = a.idx[n][ps];
-            load_row_part<KQ>(a.A[n] + (int64_t)row * J4 + KQ * q, arow[n]);
+            arow[n].load(a.A[n], a.A16[n], (int64_t)row * J4 + KQ * q);
         }
-        floatx4 C[N][RB];
+        floatx4 C[N][RB];   // C[s = 4q + v][r = 16 rb + c]
 #pragma unroll
         for (int n = 0; n < N; ++n)
 #pragma unroll
-            for (int rb = 0; rb < RB; ++rb) {
-                floatx4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                for (int t = 0; t < KQ; ++t)
-                    acc = mfma_16x16x4(arow[n][t], bop[n][rb][t], acc);
-                C[n][rb] = acc;   // C[s = 4q + v][r = 16 rb + c]
-            }
+            for (int rb = 0; rb < RB; ++rb)
+                C[n][rb] = contract(arow[n], bop[n][rb],
+                                    floatx4{0.f, 0.f, 0.f, 0.f});
         floatx4 D[N][RB];
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb) {
@@ -119,8 +113,12 @@ __global__ __launch_bounds__(256) void core_grad_kernel(CoreArgs a,
                 const int j = 16 * jb + c;
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
-                    const float e =
-                        j < J4 ? r[v] * a.A[n][(int64_t)rows4[v] * J4 + j] : 0.f;
+                    float av = 0.f;
+                    if (j < J4) {
+                        const int64_t o = (int64_t)rows4[v] * J4 + j;
+                        av = BF ? bf2f(a.A16[n][o]) : a.A[n][o];
+                    }
+                    const float e = r[v] * av;
 #pragma unroll
                     for (int rb = 0; rb < RB; ++rb)
                         grad[n][jb][rb] =
@@ -154,20 +152,23 @@ __global__ __launch_bounds__(256) void core_grad_kernel(CoreArgs a,
     if (threadIdx.x == 0) a.loss_part[blockIdx.x] = tot;
 }
 
-template <int N, int KQ, int RB>
+template <int N, int KQ, int RB, bool BF>
 static hipError_t launch_cg(const CoreArgs &a, int blocks, hipStream_t s) {
     const int64_t ntiles = (a.count + 15) / 16;
     const size_t lds = sizeof(float) * 4 * N * (4 * KQ) * (16 * RB);
-    hipLaunchKernelGGL((core_grad_kernel<N, KQ, RB>), dim3(blocks), dim3(256),
-                       lds, s, a, ntiles);
+    hipLaunchKernelGGL((core_grad_kernel<N, KQ, RB, BF>), dim3(blocks),
+                       dim3(256), lds, s, a, ntiles);
     return hipGetLastError();
 }
 
 template <int N, int KQ>
 static hipError_t launch_cg_r(const Shape &sh, const CoreArgs &a, int blocks,
                               hipStream_t s) {
-    return sh.R16 == 16 ? launch_cg<N, KQ, 1>(a, blocks, s)
-                        : launch_cg<N, KQ, 2>(a, blocks, s);
+    if (sh.bf16)
+        return sh.R16 == 16 ? launch_cg<N, KQ, 1, true>(a, blocks, s)
+                            : launch_cg<N, KQ, 2, true>(a, blocks, s);
+    return sh.R16 == 16 ? launch_cg<N, KQ, 1, false>(a, blocks, s)
+                        : launch_cg<N, KQ, 2, false>(a, blocks, s);
 }
 
 template <int N>

@@ -16,19 +16,17 @@ int eval_blocks(int64_t count) {
     return blocks < 1 ? 1 : (int)blocks;
 }
 
-template <int N, int KQ, int RB>
+template <int N, int KQ, int RB, bool BF>
 __global__ __launch_bounds__(256) void eval_kernel(EvalArgs a, int64_t ntiles) {
     constexpr int J4 = 4 * KQ;
     constexpr int R16 = 16 * RB;
     const int lane = threadIdx.x & 63, q = lane >> 4, c = lane & 15;
-    float bf[N][RB][KQ];
+    ColFrag<KQ, BF> bf[N][RB];
 #pragma unroll
     for (int n = 0; n < N; ++n)
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-            for (int t = 0; t < KQ; ++t)
-                bf[n][rb][t] = a.B[n][(KQ * q + t) * R16 + 16 * rb + c];
+            bf[n][rb].load(a.B[n], R16, q, 16 * rb + c);
     double sse = 0.0, sae = 0.0;
     const int64_t nwaves = (int64_t)gridDim.x * 4;
     for (int64_t tile = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -36,11 +34,11 @@ __global__ __launch_bounds__(256) void eval_kernel(EvalArgs a, int64_t ntiles) {
         const int64_t p = tile * 16 + c;
         const bool valid = p < a.count;
         const int64_t ps = valid ? p : a.count - 1;
-        float arow[N][KQ];
+        RowFrag<KQ, BF> arow[N];
 #pragma unroll
         for (int n = 0; n < N; ++n) {
             const int row = a.idx[n][ps];
-            load_row_part<KQ>(a.A[n] + (int64_t)row * J4 + KQ * q, arow[n]);
+            arow[n].load(a.A[n], a.A16[n], (int64_t)row * J4 + KQ * q);
         }
         float xh = 0.f;
 #pragma unroll
@@ -48,11 +46,8 @@ __global__ __launch_bounds__(256) void eval_kernel(EvalArgs a, int64_t ntiles) {
             floatx4 prod = {1.f, 1.f, 1.f, 1.f};
 #pragma unroll
             for (int n = 0; n < N; ++n) {
-                floatx4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                for (int t = 0; t < KQ; ++t)
-                    acc = mfma_16x16x4(bf[n][rb][t], arow[n][t], acc);
-                prod *= acc;
+                prod *= contract(bf[n][rb], arow[n],
+                                 floatx4{0.f, 0.f, 0.f, 0.f});
             }
             xh += (prod[0] + prod[1]) + (prod[2] + prod[3]);
         }
@@ -71,19 +66,22 @@ __global__ __launch_bounds__(256) void eval_kernel(EvalArgs a, int64_t ntiles) {
     }
 }
 
-template <int N, int KQ, int RB>
+template <int N, int KQ, int RB, bool BF>
 static hipError_t launch_ev(const EvalArgs &a, int blocks, hipStream_t s) {
     const int64_t ntiles = (a.count + 15) / 16;
-    hipLaunchKernelGGL((eval_kernel<N, KQ, RB>), dim3(blocks), dim3(256), 0, s,
-                       a, ntiles);
+    hipLaunchKernelGGL((eval_kernel<N, KQ, RB, BF>), dim3(blocks), dim3(256), 0,
+                       s, a, ntiles);
     return hipGetLastError();
 }
 
 template <int N, int KQ>
 static hipError_t launch_ev_r(const Shape &sh, const EvalArgs &a, int blocks,
                               hipStream_t s) {
-    return sh.R16 == 16 ? launch_ev<N, KQ, 1>(a, blocks, s)
-                        : launch_ev<N, KQ, 2>(a, blocks, s);
+    if (sh.bf16)
+        return sh.R16 == 16 ? launch_ev<N, KQ, 1, true>(a, blocks, s)
+                            : launch_ev<N, KQ, 2, true>(a, blocks, s);
+    return sh.R16 == 16 ? launch_ev<N, KQ, 1, false>(a, blocks, s)
+                        : launch_ev<N, KQ, 2, false>(a, blocks, s);
 }
 
 template <int N>
@@ -121,6 +119,23 @@ __global__ __launch_bounds__(256) void sumsq_kernel(const float *x, int64_t n,
         acc += (double)x[i] * (double)x[i];
     const double t = block_sum_256(acc);
     if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+__global__ void to_bf16_kernel(const float *src, uint16_t *dst, int64_t n) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += stride)
+        dst[i] = f2bf(src[i]);
+}
+
+hipError_t launch_to_bf16(const float *src, uint16_t *dst, int64_t n,
+                          hipStream_t s) {
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    if (blocks < 1) return hipSuccess;
+    hipLaunchKernelGGL(to_bf16_kernel, dim3((int)blocks), dim3(256), 0, s, src,
+                       dst, n);
+    return hipGetLastError();
 }
 
 hipError_t launch_sumsq(const float *x, int64_t n, double *part, int nblocks,

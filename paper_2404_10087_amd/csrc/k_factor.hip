@@ -38,14 +38,15 @@ int factor_grad_blocks(int32_t m) {
 
 // Per-wave state and arithmetic of one 16-sample tile (shared by the
 // deterministic and the Hogwild factor kernels).
-template <int N, int KQ, int RB>
+template <int N, int KQ, int RB, bool BF>
 struct FactorTile {
     static constexpr int J4 = 4 * KQ;
     static constexpr int R16 = 16 * RB;
     static constexpr int JB = (KQ + 3) / 4;   // 16-row output blocks of J4
     int q, c;
-    // A-operands: B^(n)T for the contraction over j, B^(n) for the one over r
-    float bf[N][RB][KQ];
+    // A-operands: B^(n)T for the contraction over j (FP32 or BF16 packs),
+    // B^(n) for the one over r (FP32)
+    ColFrag<KQ, BF> bf[N][RB];
     float bb[N][JB][RB][4];
     floatx4 D[N][RB];
 
@@ -57,10 +58,7 @@ struct FactorTile {
         for (int n = 0; n < N; ++n) {
             const float *B = Bm[n];
 #pragma unroll
-            for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-                for (int t = 0; t < KQ; ++t)
-                    bf[n][rb][t] = B[(KQ * q + t) * R16 + 16 * rb + c];
+            for (int rb = 0; rb < RB; ++rb) bf[n][rb].load(B, R16, q, 16 * rb + c);
 #pragma unroll
             for (int jb = 0; jb < JB; ++jb) {
                 const int j = 16 * jb + c;
@@ -78,25 +76,22 @@ struct FactorTile {
     // cores, D^(n) by prefix/suffix products; returns xhat (all four lanes of
     // the column hold it).
     __device__ __forceinline__ float forward(const int32_t *const *idx,
-                                             const float *const *A, int64_t ps,
-                                             int *rows) {
-        float arow[N][KQ];
+                                             const float *const *A,
+                                             const uint16_t *const *A16,
+                                             int64_t ps, int *rows) {
+        RowFrag<KQ, BF> arow[N];
 #pragma unroll
         for (int n = 0; n < N; ++n) {
             rows[n] = idx[n][ps];
-            load_row_part<KQ>(A[n] + (int64_t)rows[n] * J4 + KQ * q, arow[n]);
+            arow[n].load(A[n], A16[n], (int64_t)rows[n] * J4 + KQ * q);
         }
         floatx4 C[N][RB];
 #pragma unroll
         for (int n = 0; n < N; ++n)
 #pragma unroll
-            for (int rb = 0; rb < RB; ++rb) {
-                floatx4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                for (int t = 0; t < KQ; ++t)
-                    acc = mfma_16x16x4(bf[n][rb][t], arow[n][t], acc);
-                C[n][rb] = acc;
-            }
+            for (int rb = 0; rb < RB; ++rb)
+                C[n][rb] = contract(bf[n][rb], arow[n],
+                                    floatx4{0.f, 0.f, 0.f, 0.f});
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb) {
             floatx4 pre = {1.f, 1.f, 1.f, 1.f};
@@ -132,10 +127,10 @@ struct FactorTile {
     }
 };
 
-template <int N, int KQ, int RB>
+template <int N, int KQ, int RB, bool BF>
 __global__ __launch_bounds__(kFactorThreads) void factor_grad_kernel(
     FactorArgs a, int ntiles) {
-    using T = FactorTile<N, KQ, RB>;
+    using T = FactorTile<N, KQ, RB, BF>;
     T tl;
     tl.load_B(a.B);
     double loss = 0.0;
@@ -146,7 +141,7 @@ __global__ __launch_bounds__(kFactorThreads) void factor_grad_kernel(
         const bool valid = p < a.m;
         const int ps = valid ? p : a.m - 1;
         int rows[N];
-        const float xh = tl.forward(a.idx, a.A, ps, rows);
+        const float xh = tl.forward(a.idx, a.A, a.A16, ps, rows);
         const float r = valid ? xh - a.val[ps] : 0.f;
         if (valid && tl.q == 0) loss += 0.5 * (double)r * (double)r;
 #pragma unroll
@@ -172,7 +167,7 @@ __global__ __launch_bounds__(kFactorThreads) void factor_grad_kernel(
 // concurrent tiles race on shared rows by design. One FP64 loss per tile.
 template <int N, int KQ, int RB>
 __global__ __launch_bounds__(kFactorThreads) void hogwild_kernel(HogArgs a) {
-    using T = FactorTile<N, KQ, RB>;
+    using T = FactorTile<N, KQ, RB, false>;
     T tl;
     tl.load_B(a.B);
     const int64_t ntiles = (a.count + 15) / 16;
@@ -184,7 +179,7 @@ __global__ __launch_bounds__(kFactorThreads) void hogwild_kernel(HogArgs a) {
         const bool valid = p < a.count;
         const int64_t ps = valid ? p : a.count - 1;
         int rows[N];
-        const float xh = tl.forward(a.idx, a.A, ps, rows);
+        const float xh = tl.forward(a.idx, a.A, a.A16, ps, rows);
         const float r = valid ? xh - a.val[ps] : 0.f;
         double tl_loss = (valid && tl.q == 0) ? 0.5 * (double)r * (double)r : 0.0;
         tl_loss = wave_sum(tl_loss);
@@ -206,10 +201,10 @@ __global__ __launch_bounds__(kFactorThreads) void hogwild_kernel(HogArgs a) {
     }
 }
 
-template <int N, int KQ, int RB>
+template <int N, int KQ, int RB, bool BF>
 static hipError_t launch_fg(const FactorArgs &a, int blocks, hipStream_t s) {
     const int ntiles = (a.m + 15) / 16;
-    hipLaunchKernelGGL((factor_grad_kernel<N, KQ, RB>), dim3(blocks),
+    hipLaunchKernelGGL((factor_grad_kernel<N, KQ, RB, BF>), dim3(blocks),
                        dim3(kFactorThreads), 0, s, a, ntiles);
     return hipGetLastError();
 }
@@ -217,8 +212,11 @@ static hipError_t launch_fg(const FactorArgs &a, int blocks, hipStream_t s) {
 template <int N, int KQ>
 static hipError_t launch_fg_r(const Shape &sh, const FactorArgs &a, int blocks,
                               hipStream_t s) {
-    return sh.R16 == 16 ? launch_fg<N, KQ, 1>(a, blocks, s)
-                        : launch_fg<N, KQ, 2>(a, blocks, s);
+    if (sh.bf16)
+        return sh.R16 == 16 ? launch_fg<N, KQ, 1, true>(a, blocks, s)
+                            : launch_fg<N, KQ, 2, true>(a, blocks, s);
+    return sh.R16 == 16 ? launch_fg<N, KQ, 1, false>(a, blocks, s)
+                        : launch_fg<N, KQ, 2, false>(a, blocks, s);
 }
 
 template <int N>
@@ -319,7 +317,9 @@ __device__ __forceinline__ void finish_row(const SegArgs &a, int n, int j,
     float g = sum + (float)cnt * a.lam * av;
     if (a.apply) {
         if (a.mean) g /= (float)cnt;
-        *ap = av - a.lr * g;
+        const float nv = av - a.lr * g;
+        *ap = nv;
+        if (a.A16[n]) a.A16[n][(int64_t)row * a.J4 + j] = f2bf(nv);
     } else {
         a.grad[n][(int64_t)row * a.J4 + j] = g;
         if (j == 0) a.count[n][row] = cnt;

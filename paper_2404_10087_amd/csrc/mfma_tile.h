@@ -16,9 +16,135 @@
 namespace ft {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef short shortx4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ floatx4 mfma_16x16x4(float a, float b, floatx4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// BF16 inputs, FP32 accumulation: 16x16 output, K = 16 split as 4 bf16 per
+// lane over the four lane quads (same row/column roles as above).
+__device__ __forceinline__ floatx4 mfma_16x16x16_bf16(shortx4 a, shortx4 b,
+                                                      floatx4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+// FP32 -> BF16 with round-to-nearest-even (finite inputs), and back.
+__device__ __forceinline__ uint16_t f2bf(float f) {
+    uint32_t u = __float_as_uint(f);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t h) {
+    return __uint_as_float((uint32_t)h << 16);
+}
+
+// One lane's share of a factor row for the contraction over j: KQ
+// consecutive entries starting at KQ*q (q = lane / 16). FP32 keeps them as
+// floats (one 16x16x4 step each); BF16 packs them four to a 16x16x16 step,
+// zero-filling the last pack.
+template <int KQ, bool BF>
+struct RowFrag;
+
+template <int KQ>
+struct RowFrag<KQ, false> {
+    static constexpr int STEPS = KQ;
+    float v[KQ];
+    __device__ __forceinline__ void load(const float *A, const uint16_t *,
+                                         int64_t off) {
+        load_row(A + off);
+    }
+    __device__ __forceinline__ void load_row(const float *p);
+};
+
+template <int KQ>
+struct RowFrag<KQ, true> {
+    static constexpr int STEPS = (KQ + 3) / 4;
+    shortx4 v[STEPS];
+    __device__ __forceinline__ void load(const float *, const uint16_t *A16,
+                                         int64_t off) {
+        const uint16_t *p = A16 + off;
+        if constexpr (KQ % 4 == 0) {
+#pragma unroll
+            for (int u = 0; u < STEPS; ++u)
+                v[u] = *reinterpret_cast<const shortx4 *>(p + 4 * u);
+        } else {
+#pragma unroll
+            for (int u = 0; u < STEPS; ++u)
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    v[u][e] = 4 * u + e < KQ ? (short)p[4 * u + e] : (short)0;
+        }
+    }
+};
+
+// The matching share of a core matrix column block: entry (t) is
+// B[KQ*q + t][col], packed like RowFrag.
+template <int KQ, bool BF>
+struct ColFrag;
+
+template <int KQ>
+struct ColFrag<KQ, false> {
+    float v[KQ];
+    __device__ __forceinline__ void load(const float *B, int R16, int q,
+                                         int col) {
+#pragma unroll
+        for (int t = 0; t < KQ; ++t) v[t] = B[(KQ * q + t) * R16 + col];
+    }
+};
+
+template <int KQ>
+struct ColFrag<KQ, true> {
+    static constexpr int STEPS = (KQ + 3) / 4;
+    shortx4 v[STEPS];
+    __device__ __forceinline__ void load(const float *B, int R16, int q,
+                                         int col) {
+#pragma unroll
+        for (int u = 0; u < STEPS; ++u)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int t = 4 * u + e;
+                v[u][e] = t < KQ ? (short)f2bf(B[(KQ * q + t) * R16 + col])
+                                 : (short)0;
+            }
+    }
+};
+
+// acc += X Y over the K shares of one lane (X is the A-operand, Y the
+// B-operand of the matrix-core step).
+template <int KQ>
+__device__ __forceinline__ floatx4 contract(const ColFrag<KQ, false> &x,
+                                            const RowFrag<KQ, false> &y,
+                                            floatx4 acc) {
+#pragma unroll
+    for (int t = 0; t < KQ; ++t) acc = mfma_16x16x4(x.v[t], y.v[t], acc);
+    return acc;
+}
+template <int KQ>
+__device__ __forceinline__ floatx4 contract(const ColFrag<KQ, true> &x,
+                                            const RowFrag<KQ, true> &y,
+                                            floatx4 acc) {
+#pragma unroll
+    for (int u = 0; u < (KQ + 3) / 4; ++u)
+        acc = mfma_16x16x16_bf16(x.v[u], y.v[u], acc);
+    return acc;
+}
+template <int KQ>
+__device__ __forceinline__ floatx4 contract(const RowFrag<KQ, false> &x,
+                                            const ColFrag<KQ, false> &y,
+                                            floatx4 acc) {
+#pragma unroll
+    for (int t = 0; t < KQ; ++t) acc = mfma_16x16x4(x.v[t], y.v[t], acc);
+    return acc;
+}
+template <int KQ>
+__device__ __forceinline__ floatx4 contract(const RowFrag<KQ, true> &x,
+                                            const ColFrag<KQ, true> &y,
+                                            floatx4 acc) {
+#pragma unroll
+    for (int u = 0; u < (KQ + 3) / 4; ++u)
+        acc = mfma_16x16x16_bf16(x.v[u], y.v[u], acc);
+    return acc;
 }
 
 // Load KQ consecutive floats (16-byte aligned when KQ is a multiple of 4).
@@ -41,6 +167,11 @@ __device__ __forceinline__ void load_row_part(const float *p, float (&out)[KQ]) 
 #pragma unroll
         for (int t = 0; t < KQ; ++t) out[t] = p[t];
     }
+}
+
+template <int KQ>
+__device__ __forceinline__ void RowFrag<KQ, false>::load_row(const float *p) {
+    load_row_part<KQ>(p, v);
 }
 
 // Sum over the four lanes that share l % 16 (lanes l, l^16, l^32, l^48).

@@ -163,9 +163,29 @@ class Tensor:
         return len(self.dims)
 
 
-def make_tensor(w, seed=None):
-    """Build the synthetic tensor of a Workload (see configs.py)."""
+def make_tensor(w, seed=None, cache_dir=None):
+    """Build the synthetic tensor of a Workload (see configs.py). With
+    cache_dir, a tensor generated before for the same workload and seed is
+    loaded from there (a plain .npz, no pickles) instead."""
     seed = w.data_seed if seed is None else seed
+    if cache_dir:
+        import hashlib
+        import os
+        key = hashlib.sha256(repr((w, seed)).encode()).hexdigest()[:16]
+        path = os.path.join(cache_dir, f"tensor_{key}.npz")
+        if os.path.exists(path):
+            z = np.load(path, allow_pickle=False)
+            return Tensor(dims=list(w.dims), train_idx=z["train_idx"],
+                          train_val=z["train_val"], test_idx=z["test_idx"],
+                          test_val=z["test_val"],
+                          meta={"workload": w.name, "seed": seed})
+        T = make_tensor(w, seed)
+        os.makedirs(cache_dir, exist_ok=True)
+        tmp = path + ".tmp.npz"
+        np.savez(tmp, train_idx=T.train_idx, train_val=T.train_val,
+                 test_idx=T.test_idx, test_val=T.test_val)
+        os.replace(tmp, path)
+        return T
     rng = _rng(seed)
     if w.index_dist == "uniform":
         idx = uniform_distinct(rng, w.dims, w.nnz)

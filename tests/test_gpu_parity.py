@@ -352,3 +352,52 @@ def test_fast_mode_rejects_minibatch_not_multiple_of_tile():
     with pytest.raises(FtError) as e:
         ft.set_options(deterministic=0, minibatch=500)
     assert e.value.status == 1
+
+
+# ----------------------------------------------------------------- BF16
+@pytest.mark.parametrize("name", ["c0", "zipf", "order5_J32_R32"])
+def test_bf16_contraction_training_within_one_percent(name):
+    """BF16 contraction (FP32 masters and updates): after free-running
+    alternating epochs the test RMSE is within 1% of the FP64 oracle's."""
+    w = W[name]
+    ft, T, A0, B0 = setup(w)
+    ft.set_options(precision=1)
+    A, B = f64(A0), f64(B0)
+    tv = T.train_val.astype(np.float64)
+    sv = T.test_val.astype(np.float64)
+    osse0, _ = oracle.residual_stats(A, B, T.test_idx, sv)
+    assert ft.rmse(FT_TEST) == pytest.approx(np.sqrt(osse0 / len(sv)),
+                                             rel=1e-2)
+    for ep in range(w.epochs):
+        p = perm_for(w, T, ep)
+        ft.set_epoch_order(p)
+        ft.epoch_factors()
+        ft.epoch_core()
+        oracle.factor_epoch(A, B, T.train_idx, tv, p, w.M, w.lr_A, w.lam_A,
+                            w.row_mean)
+        oracle.core_epoch(A, B, T.train_idx, tv, w.lr_B, w.lam_B)
+    osse, _ = oracle.residual_stats(A, B, T.test_idx, sv)
+    assert ft.rmse(FT_TEST) == pytest.approx(np.sqrt(osse / len(sv)),
+                                             rel=1e-2)
+    # switching back to FP32 evaluates the FP32 masters
+    ft.set_options(precision=0)
+    A1, B1 = ft.get_params()
+    gsse, _ = oracle.residual_stats(f64(A1), f64(B1), T.test_idx, sv)
+    assert ft.rmse(FT_TEST) == pytest.approx(np.sqrt(gsse / len(sv)),
+                                             rel=LOSS_RTOL)
+
+
+def test_bf16_shadow_follows_set_params():
+    w = W["c0"]
+    ft, T, A0, B0 = setup(w, with_test=False)
+    ft.set_options(precision=1)
+    r1 = ft.rmse(FT_TRAIN)
+    A2, B2 = synth.init_params(77, w.dims, w.J, w.R, 0.4)
+    ft.set_params(A2, B2)
+    osse, _ = oracle.residual_stats(f64(A2), f64(B2), T.train_idx,
+                                    T.train_val.astype(np.float64))
+    r2 = ft.rmse(FT_TRAIN)
+    assert r2 != r1
+    assert r2 == pytest.approx(np.sqrt(osse / T.train_idx.shape[1]), rel=1e-2)
+    with pytest.raises(FtError):
+        ft.set_options(deterministic=0)

@@ -18,6 +18,10 @@
 
 using namespace ft;
 
+namespace ft {
+thread_local ExtEvents g_ext_events;
+}
+
 namespace {
 thread_local std::string g_create_error = "no error";
 
@@ -132,30 +136,43 @@ static int64_t nminibatches(const ft_handle *h) {
     return (h->nnz[FT_TRAIN] + h->opt.minibatch - 1) / h->opt.minibatch;
 }
 
-static void prof_begin(ft_handle *h, int kind) {
-    if (!h->prof) return;
-    hipEvent_t a;
+static hipEvent_t pool_event(ft_handle *h) {
+    hipEvent_t e = nullptr;
     if (h->pool.empty()) {
-        if (hipEventCreate(&a) != hipSuccess) return;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
     } else {
-        a = h->pool.back();
+        e = h->pool.back();
         h->pool.pop_back();
     }
+    return e;
+}
+
+// Bracketing form (several kernels in one class): markers on the stream.
+static void prof_begin(ft_handle *h, int kind) {
+    if (!h->prof) return;
+    hipEvent_t a = pool_event(h);
+    if (!a) return;
     (void)hipEventRecord(a, h->stream);
     h->pending.push_back({kind, a, nullptr});
 }
 
 static void prof_end(ft_handle *h) {
     if (!h->prof || h->pending.empty() || h->pending.back().b) return;
-    hipEvent_t b;
-    if (h->pool.empty()) {
-        if (hipEventCreate(&b) != hipSuccess) return;
-    } else {
-        b = h->pool.back();
-        h->pool.pop_back();
-    }
+    hipEvent_t b = pool_event(h);
+    if (!b) return;
     (void)hipEventRecord(b, h->stream);
     h->pending.back().b = b;
+}
+
+// Single-kernel form: the launch itself records the two events.
+static void prof_ext(ft_handle *h, int kind) {
+    g_ext_events = ExtEvents{};
+    if (!h->prof) return;
+    hipEvent_t a = pool_event(h), b = pool_event(h);
+    if (!a || !b) return;
+    h->pending.push_back({kind, a, b});
+    g_ext_events.start = a;
+    g_ext_events.stop = b;
 }
 
 static ft_status prof_collect(ft_handle *h) {
@@ -180,6 +197,11 @@ struct Launch {
     ft_handle *h;
     Launch(ft_handle *hh, int kind) : h(hh) { prof_begin(h, kind); }
     ~Launch() { prof_end(h); }
+};
+
+struct LaunchExt {
+    LaunchExt(ft_handle *h, int kind) { prof_ext(h, kind); }
+    ~LaunchExt() { g_ext_events = ExtEvents{}; }
 };
 
 // SplitMix64 (Steele, Lea & Flood, 2014) and the Box-Muller transform for the
@@ -652,7 +674,7 @@ static ft_status run_minibatch(ft_handle *h, int64_t b, int apply,
     fa.loss_part = loss_part;
     int nb = 0;
     {
-        Launch L(h, FT_K_FACTOR_GRAD);
+        LaunchExt L(h, FT_K_FACTOR_GRAD);
         HIPCHK(h, launch_factor_grad(h->sh, fa, &nb, h->stream));
     }
     SegArgs sa{};
@@ -676,11 +698,11 @@ static ft_status run_minibatch(ft_handle *h, int64_t b, int apply,
     sa.mean = h->opt.row_scale == FT_ROW_MEAN;
     sa.apply = apply;
     {
-        Launch L(h, FT_K_SEG_REDUCE);
+        LaunchExt L(h, FT_K_SEG_REDUCE);
         HIPCHK(h, launch_seg_reduce(sa, h->stream));
     }
     {
-        Launch L(h, FT_K_SEG_FIXUP);
+        LaunchExt L(h, FT_K_SEG_FIXUP);
         HIPCHK(h, launch_seg_fixup(sa, h->stream));
     }
     return FT_OK;
@@ -725,7 +747,7 @@ static ft_status epoch_factors_fast(ft_handle *h, std::vector<double> &losses) {
     ha.lam = (float)h->opt.lambda_A;
     ha.tile_loss = h->tile_loss;
     {
-        Launch L(h, FT_K_HOGWILD);
+        LaunchExt L(h, FT_K_HOGWILD);
         HIPCHK(h, launch_hogwild(h->sh, ha, h->stream));
     }
     HIPCHK(h, launch_sum_blocks(h->tile_loss, (int)tpm, (int)nmb, h->mb_loss,
@@ -872,7 +894,7 @@ static ft_status core_pass(ft_handle *h, const int32_t *const *idx,
     ca.part = h->core_part;
     ca.loss_part = h->dpart;
     {
-        Launch L(h, FT_K_CORE_GRAD);
+        LaunchExt L(h, FT_K_CORE_GRAD);
         HIPCHK(h, launch_core_grad(h->sh, ca, nb, h->stream));
     }
     CoreUpdateArgs ua{};
@@ -885,7 +907,7 @@ static ft_status core_pass(ft_handle *h, const int32_t *const *idx,
     ua.lam = (float)h->opt.lambda_B;
     ua.apply = apply;
     {
-        Launch L(h, FT_K_CORE_UPDATE);
+        LaunchExt L(h, FT_K_CORE_UPDATE);
         HIPCHK(h, launch_core_update(h->sh, ua, h->stream));
     }
     HIPCHK(h, launch_sum_blocks(h->dpart, nb, 1, loss_dev, h->stream));
@@ -980,7 +1002,7 @@ extern "C" ft_status ft_eval(ft_handle *h, ft_set which, double *sse,
         ea.count = count;
         ea.part = h->dpart;
         {
-            Launch L(h, FT_K_EVAL);
+            LaunchExt L(h, FT_K_EVAL);
             HIPCHK(h, launch_eval(h->sh, ea, nb, h->stream));
         }
         HIPCHK(h, launch_sum_blocks(h->dpart, nb, 2, h->scal, h->stream));

@@ -2,10 +2,31 @@
 // runtime (ft_api.cpp) and the HIP kernels of the sparse FastTucker library.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 namespace ft {
+
+// Timing of single-kernel launches: when the host sets these (profiling on),
+// the next launch records them exactly at the kernel's start and end
+// (hipExtLaunchKernelGGL) and clears them.
+struct ExtEvents {
+    hipEvent_t start = nullptr, stop = nullptr;
+};
+extern thread_local ExtEvents g_ext_events;
+
+#define FT_LAUNCH(kernel, grid, block, shm, stream, ...)                      \
+    do {                                                                      \
+        if (::ft::g_ext_events.start) {                                       \
+            hipExtLaunchKernelGGL(kernel, grid, block, shm, stream,           \
+                                  ::ft::g_ext_events.start,                   \
+                                  ::ft::g_ext_events.stop, 0, __VA_ARGS__);   \
+            ::ft::g_ext_events = ::ft::ExtEvents{};                           \
+        } else {                                                              \
+            hipLaunchKernelGGL(kernel, grid, block, shm, stream, __VA_ARGS__); \
+        }                                                                     \
+    } while (0)
 
 constexpr int kMaxOrder = 5;
 constexpr int kMaxJ = 32;

@@ -156,7 +156,7 @@ template <int N, int KQ, int RB, bool BF>
 static hipError_t launch_cg(const CoreArgs &a, int blocks, hipStream_t s) {
     const int64_t ntiles = (a.count + 15) / 16;
     const size_t lds = sizeof(float) * 4 * N * (4 * KQ) * (16 * RB);
-    hipLaunchKernelGGL((core_grad_kernel<N, KQ, RB, BF>), dim3(blocks),
+    FT_LAUNCH((core_grad_kernel<N, KQ, RB, BF>), dim3(blocks),
                        dim3(256), lds, s, a, ntiles);
     return hipGetLastError();
 }
@@ -230,7 +230,7 @@ __global__ __launch_bounds__(256) void core_update_kernel(CoreUpdateArgs a,
 hipError_t launch_core_update(const Shape &sh, const CoreUpdateArgs &a,
                               hipStream_t s) {
     const int E = sh.N * sh.J4 * sh.R16;
-    hipLaunchKernelGGL(core_update_kernel, dim3((E + 63) / 64), dim3(256), 0, s,
+    FT_LAUNCH(core_update_kernel, dim3((E + 63) / 64), dim3(256), 0, s,
                        a, E, sh.J4, sh.R16);
     return hipGetLastError();
 }

@@ -69,7 +69,7 @@ __global__ __launch_bounds__(256) void eval_kernel(EvalArgs a, int64_t ntiles) {
 template <int N, int KQ, int RB, bool BF>
 static hipError_t launch_ev(const EvalArgs &a, int blocks, hipStream_t s) {
     const int64_t ntiles = (a.count + 15) / 16;
-    hipLaunchKernelGGL((eval_kernel<N, KQ, RB, BF>), dim3(blocks), dim3(256), 0,
+    FT_LAUNCH((eval_kernel<N, KQ, RB, BF>), dim3(blocks), dim3(256), 0,
                        s, a, ntiles);
     return hipGetLastError();
 }

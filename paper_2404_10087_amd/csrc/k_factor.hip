@@ -14,11 +14,11 @@
 //
 // seg_reduce_kernel / seg_fixup_kernel: the deterministic row reduction.
 // The builder has sorted every minibatch's samples by row (ties in minibatch
-// order). Each group of lanes (one lane per column j) walks a fixed chunk of
-// kSegChunk sorted samples in order, summing g per row; rows whose samples
-// all lie in the chunk are finished there, the partial sums of rows that
-// cross a chunk edge are finished by the fix-up kernel in chunk order. A
-// finished row takes
+// order). A wave takes a fixed chunk of kSegChunk sorted samples, one per
+// lane, and sums each row's gradients by a segmented scan across its lanes;
+// rows whose samples all lie in the chunk are finished there, the fragment
+// sums of rows that cross a chunk edge are combined by the fix-up kernel in
+// a fixed order. A finished row takes
 //     G = sum_s g_s + k * lambda_A * a,   a <- a - lr_A * G   (or G / k)
 // No floating-point atomics are used, so results are bitwise reproducible.
 #include "ft_internal.h"
@@ -204,7 +204,7 @@ __global__ __launch_bounds__(kFactorThreads) void hogwild_kernel(HogArgs a) {
 template <int N, int KQ, int RB, bool BF>
 static hipError_t launch_fg(const FactorArgs &a, int blocks, hipStream_t s) {
     const int ntiles = (a.m + 15) / 16;
-    hipLaunchKernelGGL((factor_grad_kernel<N, KQ, RB, BF>), dim3(blocks),
+    FT_LAUNCH((factor_grad_kernel<N, KQ, RB, BF>), dim3(blocks),
                        dim3(kFactorThreads), 0, s, a, ntiles);
     return hipGetLastError();
 }
@@ -250,7 +250,7 @@ hipError_t launch_factor_grad(const Shape &sh, const FactorArgs &a, int *nblocks
 
 template <int N, int KQ, int RB>
 static hipError_t launch_hw(const HogArgs &a, int blocks, hipStream_t s) {
-    hipLaunchKernelGGL((hogwild_kernel<N, KQ, RB>), dim3(blocks),
+    FT_LAUNCH((hogwild_kernel<N, KQ, RB>), dim3(blocks),
                        dim3(kFactorThreads), 0, s, a);
     return hipGetLastError();
 }
@@ -297,154 +297,189 @@ hipError_t launch_hogwild(const Shape &sh, const HogArgs &a, hipStream_t s) {
 }
 
 // ------------------------------------------------------------ row reduction
-__device__ __forceinline__ void finish_row(const SegArgs &a, int n, int j,
-                                           bool col, uint32_t row, float sum,
+// Finish one row of mode n whose summed per-sample gradient g[0..J4) over
+// cnt occurrences is complete; start is the sorted index of its first
+// occurrence. Writes the whole row (one lane).
+template <int J4>
+__device__ __forceinline__ void finish_row(const SegArgs &a, int n,
+                                           uint32_t row, const float (&g)[J4],
                                            int cnt, int start) {
-    if (!col) return;
+    const int64_t off = (int64_t)row * J4;
     if (a.apply == 2) {
         // autograd: gradient of the data term only, times grad_out
-        const float g = sum * (a.scale ? *a.scale : 1.f);
-        if (a.grad[n]) a.grad[n][(int64_t)row * a.J4 + j] = g;
+        const float sc = a.scale ? *a.scale : 1.f;
+        float o[J4];
+#pragma unroll
+        for (int j = 0; j < J4; ++j) o[j] = g[j] * sc;
+        if (a.grad[n]) store_row<J4>(a.grad[n] + off, o);
         if (a.uniq_grad[n]) {
             const uint32_t ord = a.ordinal[n][start];
-            a.uniq_grad[n][(int64_t)ord * a.J4 + j] = g;
-            if (j == 0 && a.uniq_rows[n]) a.uniq_rows[n][ord] = (int32_t)row;
+            store_row<J4>(a.uniq_grad[n] + (int64_t)ord * J4, o);
+            if (a.uniq_rows[n]) a.uniq_rows[n][ord] = (int32_t)row;
         }
         return;
     }
-    float *ap = a.A[n] + (int64_t)row * a.J4 + j;
-    const float av = *ap;
-    float g = sum + (float)cnt * a.lam * av;
+    float av[J4];
+    load_row_part<J4>(a.A[n] + off, av);
+    float o[J4];
+#pragma unroll
+    for (int j = 0; j < J4; ++j) o[j] = g[j] + (float)cnt * a.lam * av[j];
     if (a.apply) {
-        if (a.mean) g /= (float)cnt;
-        const float nv = av - a.lr * g;
-        *ap = nv;
-        if (a.A16[n]) a.A16[n][(int64_t)row * a.J4 + j] = f2bf(nv);
+        const float inv = a.mean ? 1.f / (float)cnt : 1.f;
+#pragma unroll
+        for (int j = 0; j < J4; ++j) o[j] = av[j] - a.lr * (a.mean ? o[j] * inv : o[j]);
+        store_row<J4>(a.A[n] + off, o);
+        if (a.A16[n]) {
+#pragma unroll
+            for (int j = 0; j < J4; ++j) a.A16[n][off + j] = f2bf(o[j]);
+        }
     } else {
-        a.grad[n][(int64_t)row * a.J4 + j] = g;
-        if (j == 0) a.count[n][row] = cnt;
+        store_row<J4>(a.grad[n] + off, o);
+        a.count[n][row] = cnt;
     }
 }
 
-template <int LP>
+// One wave per chunk of 64 sorted samples of one mode; lane l holds sample
+// i0 + l with its whole gradient row. A segmented inclusive scan across the
+// lanes (Hillis-Steele, steps 1..32, a lane adds the value d lanes below when
+// that lane belongs to its segment) leaves every row's chunk-local sum in
+// the lane of its last sample; that lane finishes the row if all of its
+// samples are in the chunk, or stores the fragment sum for the fix-up. The
+// addition tree depends only on the data, so results are reproducible.
+template <int KQ>
 __global__ __launch_bounds__(256) void seg_reduce_kernel(SegArgs a) {
-    const int g = blockIdx.x * (256 / LP) + threadIdx.x / LP;
-    const int j = threadIdx.x % LP;
-    if (g >= a.N * a.nchunks) return;
-    const int n = g / a.nchunks, c = g % a.nchunks;
-    const int i0 = c * kSegChunk;
+    constexpr int J4 = 4 * KQ;
+    const int lane = threadIdx.x & 63;
+    const int gw = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (gw >= a.N * a.nchunks) return;           // uniform per wave
+    const int n = gw / a.nchunks, c = gw % a.nchunks;
+    const int i0 = c * kSegChunk, i = i0 + lane;
     const int i1 = min(i0 + kSegChunk, a.m);
+    const bool valid = i < i1;
     const uint32_t *rows = a.rows[n];
-    const uint32_t *pos = a.pos[n];
-    const float *G = a.G + (int64_t)n * a.m * a.J4;
-    const bool col = j < a.J4;
-    const uint32_t first_row = rows[i0];
-    const bool starts_before = i0 > 0 && rows[i0 - 1] == first_row;
-    const bool continues_after = i1 < a.m && rows[i1] == rows[i1 - 1];
-    float *first = a.first + ((int64_t)n * a.nchunks + c) * a.J4 + j;
-    float *last = a.last + ((int64_t)n * a.nchunks + c) * a.J4 + j;
-
-    float acc = 0.f;
-    int cnt = 0;
-    int start = i0;
-    uint32_t cur = first_row;
-    bool is_first = true;
-    for (int base = i0; base < i1; base += 8) {
-        uint32_t rr[8];
-        float gg[8];
+    const uint32_t row = valid ? rows[i] : 0xffffffffu;
+    const uint32_t below = __shfl_up(row, 1);
+    const bool head = lane == 0 || row != below;
+    int s = head ? lane : 0;                      // first lane of my segment
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int i = base + u;
-            rr[u] = i < i1 ? rows[i] : cur;
-            gg[u] = (i < i1 && col) ? G[(int64_t)pos[i] * a.J4 + j] : 0.f;
-        }
+    for (int d = 1; d < 64; d <<= 1) {
+        const int t = __shfl_up(s, d);
+        if (lane >= d) s = max(s, t);
+    }
+    float g[J4];
+    if (valid) {
+        load_row_part<J4>(a.G + ((int64_t)n * a.m + a.pos[n][i]) * J4, g);
+    } else {
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            if (base + u >= i1) break;
-            if (rr[u] != cur) {
-                // close the fragment of row `cur`; it cannot continue past the
-                // chunk, so it is finished here unless it started before
-                if (is_first && starts_before) {
-                    if (col) *first = acc;
-                } else {
-                    finish_row(a, n, j, col, cur, acc, cnt, start);
-                }
-                acc = 0.f;
-                cnt = 0;
-                start = base + u;
-                cur = rr[u];
-                is_first = false;
-            }
-            acc += gg[u];
-            ++cnt;
+        for (int j = 0; j < J4; ++j) g[j] = 0.f;
+    }
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const bool take = lane - d >= s;
+#pragma unroll
+        for (int j = 0; j < J4; ++j) {
+            const float t = __shfl_up(g[j], d);
+            if (take) g[j] += t;
         }
     }
-    const bool span_before = is_first && starts_before;
-    if (!span_before && !continues_after) {
-        finish_row(a, n, j, col, cur, acc, cnt, start);
-    } else if (col) {
-        if (is_first) *first = acc;
-        *last = acc;
+    const uint32_t above = __shfl_down(row, 1);
+    const bool last_in_chunk = i == i1 - 1;
+    const bool tail = valid && (last_in_chunk || above != row);
+    if (!tail) return;
+    const bool first_frag = s == 0;
+    const bool starts_before = first_frag && i0 > 0 && rows[i0 - 1] == row;
+    const bool continues_after = last_in_chunk && i1 < a.m && rows[i1] == row;
+    if (!starts_before && !continues_after) {
+        finish_row<J4>(a, n, row, g, lane - s + 1, i0 + s);
+        return;
     }
+    const int64_t slot = ((int64_t)n * a.nchunks + c) * J4;
+    if (first_frag) store_row<J4>(a.first + slot, g);
+    if (last_in_chunk) store_row<J4>(a.last + slot, g);
 }
 
-__global__ __launch_bounds__(256) void seg_fixup_kernel(SegArgs a, int LP) {
-    const int g = blockIdx.x * (256 / LP) + threadIdx.x / LP;
-    const int j = threadIdx.x % LP;
-    if (g >= a.N * a.nchunks) return;
-    const int n = g / a.nchunks, c = g % a.nchunks;
+// One wave per chunk: if the chunk's first sample belongs to a row that
+// started in an earlier chunk and ends in this one, sum the row's fragment
+// sums (last fragment of its first chunk, whole middle chunks, first fragment
+// of this chunk) with 64 lanes at a time and a fixed reduction tree.
+template <int KQ>
+__global__ __launch_bounds__(256) void seg_fixup_kernel(SegArgs a) {
+    constexpr int J4 = 4 * KQ;
+    const int lane = threadIdx.x & 63;
+    const int gw = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (gw >= a.N * a.nchunks) return;
+    const int n = gw / a.nchunks, c = gw % a.nchunks;
     const int i0 = c * kSegChunk;
     if (i0 == 0) return;
     const uint32_t *rows = a.rows[n];
     const uint32_t row = rows[i0];
-    if (rows[i0 - 1] != row) return;              // segment starts in c
+    if (rows[i0 - 1] != row) return;              // row starts in this chunk
     const int i1 = min(i0 + kSegChunk, a.m);
     if (i1 < a.m && rows[i1 - 1] == row && rows[i1] == row)
-        return;                                   // segment ends after c
+        return;                                   // row ends after this chunk
     int lo = 0, hi = i0;                          // first sorted index of row
     while (lo < hi) {
         const int mid = (lo + hi) >> 1;
         if (rows[mid] < row) lo = mid + 1; else hi = mid;
     }
     const int start = lo;
-    int end = i0;
-    while (end < i1 && rows[end] == row) ++end;
-    const bool col = j < a.J4;
-    if (!col) return;
+    const bool same = i0 + lane < i1 && rows[i0 + lane] == row;
+    const int end = i0 + __popcll(__ballot(same));
     const int c0 = start / kSegChunk;
-    const float *first = a.first + (int64_t)n * a.nchunks * a.J4 + j;
-    const float *last = a.last + (int64_t)n * a.nchunks * a.J4 + j;
-    float acc = last[(int64_t)c0 * a.J4];
-    for (int cc = c0 + 1; cc <= c; ++cc) acc += first[(int64_t)cc * a.J4];
-    finish_row(a, n, j, col, row, acc, end - start, start);
+    const int nparts = c - c0 + 1;
+    float g[J4];
+#pragma unroll
+    for (int j = 0; j < J4; ++j) g[j] = 0.f;
+    for (int k = lane; k < nparts; k += 64) {
+        const int cc = c0 + k;
+        const float *src = (k == 0 ? a.last : a.first) +
+                           ((int64_t)n * a.nchunks + cc) * J4;
+        float t[J4];
+        load_row_part<J4>(src, t);
+#pragma unroll
+        for (int j = 0; j < J4; ++j) g[j] += t[j];
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1)
+#pragma unroll
+        for (int j = 0; j < J4; ++j) g[j] += __shfl_xor(g[j], d);
+    if (lane == 0) finish_row<J4>(a, n, row, g, end - start, start);
 }
 
-static int lanes_per_group(int J4) {
-    int lp = 4;
-    while (lp < J4) lp <<= 1;
-    return lp;
+template <int KQ>
+static hipError_t launch_seg_pair(const SegArgs &a, bool fixup,
+                                  hipStream_t s) {
+    const int waves = a.N * a.nchunks;
+    const int blocks = (waves + 3) / 4;
+    if (fixup)
+        FT_LAUNCH(seg_fixup_kernel<KQ>, dim3(blocks), dim3(256), 0, s,
+                           a);
+    else
+        FT_LAUNCH(seg_reduce_kernel<KQ>, dim3(blocks), dim3(256), 0,
+                           s, a);
+    return hipGetLastError();
+}
+
+static hipError_t launch_seg(const SegArgs &a, bool fixup, hipStream_t s) {
+    switch (a.J4) {
+    case 4: return launch_seg_pair<1>(a, fixup, s);
+    case 8: return launch_seg_pair<2>(a, fixup, s);
+    case 12: return launch_seg_pair<3>(a, fixup, s);
+    case 16: return launch_seg_pair<4>(a, fixup, s);
+    case 20: return launch_seg_pair<5>(a, fixup, s);
+    case 24: return launch_seg_pair<6>(a, fixup, s);
+    case 28: return launch_seg_pair<7>(a, fixup, s);
+    case 32: return launch_seg_pair<8>(a, fixup, s);
+    }
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_seg_reduce(const SegArgs &a, hipStream_t s) {
-    const int lp = lanes_per_group(a.J4);
-    const int groups = a.N * a.nchunks;
-    const int blocks = (groups + 256 / lp - 1) / (256 / lp);
-    switch (lp) {
-    case 4: hipLaunchKernelGGL(seg_reduce_kernel<4>, dim3(blocks), dim3(256), 0, s, a); break;
-    case 8: hipLaunchKernelGGL(seg_reduce_kernel<8>, dim3(blocks), dim3(256), 0, s, a); break;
-    case 16: hipLaunchKernelGGL(seg_reduce_kernel<16>, dim3(blocks), dim3(256), 0, s, a); break;
-    case 32: hipLaunchKernelGGL(seg_reduce_kernel<32>, dim3(blocks), dim3(256), 0, s, a); break;
-    default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
+    return launch_seg(a, false, s);
 }
 
 hipError_t launch_seg_fixup(const SegArgs &a, hipStream_t s) {
-    const int lp = lanes_per_group(a.J4);
-    const int groups = a.N * a.nchunks;
-    const int blocks = (groups + 256 / lp - 1) / (256 / lp);
-    hipLaunchKernelGGL(seg_fixup_kernel, dim3(blocks), dim3(256), 0, s, a, lp);
-    return hipGetLastError();
+    return launch_seg(a, true, s);
 }
 
 // ------------------------------------------------------------ block sums

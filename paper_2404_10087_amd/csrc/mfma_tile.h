@@ -169,6 +169,20 @@ __device__ __forceinline__ void load_row_part(const float *p, float (&out)[KQ]) 
     }
 }
 
+// Store N consecutive floats (16-byte aligned when N is a multiple of 4).
+template <int NF>
+__device__ __forceinline__ void store_row(float *p, const float (&v)[NF]) {
+    if constexpr (NF % 4 == 0) {
+#pragma unroll
+        for (int t = 0; t < NF; t += 4)
+            *reinterpret_cast<float4 *>(p + t) =
+                make_float4(v[t], v[t + 1], v[t + 2], v[t + 3]);
+    } else {
+#pragma unroll
+        for (int t = 0; t < NF; ++t) p[t] = v[t];
+    }
+}
+
 template <int KQ>
 __device__ __forceinline__ void RowFrag<KQ, false>::load_row(const float *p) {
     load_row_part<KQ>(p, v);

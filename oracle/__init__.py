@@ -4,6 +4,7 @@ Test infrastructure: only the test suite, the smoke check and the benchmark's
 CPU-baseline leg use this package. It shares no code with the HIP library.
 """
 from .oracle import (  # noqa: F401
-    build, lib_path, predict, residual_stats, loss, factor_minibatch,
+    build, lib_path, use_library, predict, residual_stats, loss,
+    factor_minibatch,
     factor_epoch, core_grad, core_epoch,
 )

@@ -39,11 +39,23 @@ def build(force=False):
     return _LIB
 
 
+def use_library(path=None):
+    """Load the oracle from another build of ft_oracle.c (None: the default
+    one). Only the test suite's planted-mistake check uses this."""
+    global _lib, _override
+    _override = path
+    _lib = None
+
+
+_override = None
+
+
 def _load():
     global _lib
     if _lib is None:
-        build()
-        lib = C.CDLL(_LIB)
+        if _override is None:
+            build()
+        lib = C.CDLL(_override or _LIB)
         pp = C.POINTER(_dp)
         lib.orc_predict.argtypes = [C.c_int, _i32p, C.c_int32, pp, pp,
                                     C.c_int64, _i32p, _dp]

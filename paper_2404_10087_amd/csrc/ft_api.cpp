@@ -55,6 +55,7 @@ struct ft_handle {
     bool use_user_perm = false;
     uint32_t *user_perm = nullptr;
     uint32_t *perm = nullptr;
+    uint32_t *rec = nullptr;          // training records (record_words(N) words)
     int32_t *pidx[kMaxOrder] = {};
     float *pval = nullptr;
     uint32_t *sk[2][kMaxOrder] = {};
@@ -68,8 +69,11 @@ struct ft_handle {
     // factor-phase scratch
     float *G = nullptr;
     size_t G_cap = 0;
-    float *first = nullptr, *last = nullptr;
-    size_t fl_cap = 0;
+    int2 *xlist = nullptr;            // crossing rows per minibatch and mode
+    size_t xlist_cap = 0;
+    int32_t *xcount = nullptr;
+    size_t xcount_cap = 0;
+    int xcap = 1;
     double *mb_part = nullptr;
     size_t mb_part_cap = 0;
     double *mb_loss = nullptr;
@@ -242,6 +246,7 @@ static void release(ft_handle *h) {
         dfree(h->A[n]);
         dfree(h->B[n]);
         dfree(h->A16[n]);
+
         for (int s = 0; s < 2; ++s) {
             dfree(h->idx[s][n]);
             dfree(h->sk[s][n]);
@@ -253,11 +258,12 @@ static void release(ft_handle *h) {
     dfree(h->val[1]);
     dfree(h->user_perm);
     dfree(h->perm);
+    dfree(h->rec);
     dfree(h->pval);
     dfree(h->counts);
     dfree(h->G);
-    dfree(h->first);
-    dfree(h->last);
+    dfree(h->xlist);
+    dfree(h->xcount);
     dfree(h->mb_part);
     dfree(h->mb_loss);
     dfree(h->tile_loss);
@@ -524,6 +530,13 @@ extern "C" ft_status ft_set_nonzeros(ft_handle *h, ft_set which, int64_t nnz,
         h->perm = nullptr;
         dfree(h->pval);
         h->pval = nullptr;
+        dfree(h->rec);
+        h->rec = nullptr;
+        const int rw = record_words(h->N);
+        HIPCHK(h, hipMalloc(&h->rec, sizeof(uint32_t) * rw * nnz));
+        HIPCHK(h, launch_pack_records(h->N, h->idx[FT_TRAIN], h->val[FT_TRAIN],
+                                      nnz, h->rec, rw, h->stream));
+        HIPCHK(h, hipStreamSynchronize(h->stream));
         HIPCHK(h, hipMalloc(&h->perm, sizeof(uint32_t) * nnz));
         HIPCHK(h, hipMalloc(&h->pval, sizeof(float) * nnz));
         for (int n = 0; n < h->N; ++n) {
@@ -595,7 +608,7 @@ static ft_status draw_order(ft_handle *h, uint64_t salt) {
 
 static ft_status permute_streams(ft_handle *h) {
     Launch L(h, FT_K_PERMUTE);
-    HIPCHK(h, launch_permute(h->N, h->idx[FT_TRAIN], h->val[FT_TRAIN], h->perm,
+    HIPCHK(h, launch_permute(h->N, h->rec, record_words(h->N), h->perm,
                              h->nnz[FT_TRAIN], h->pidx, h->pval, h->stream));
     return FT_OK;
 }
@@ -635,6 +648,19 @@ static ft_status build_minibatches(ft_handle *h) {
         HIPCHK(h, launch_sort_pass(p, h->stream));
     }
     h->sort_final = cur;
+    CrossArgs cx{};
+    cx.N = h->N;
+    cx.nnz = nnz;
+    cx.M = M;
+    cx.nseg = nseg;
+    cx.xcap = cross_capacity(std::min<int64_t>(M, nnz));
+    for (int n = 0; n < h->N; ++n) cx.rows[n] = h->sk[cur][n];
+    HIPCHK(h, ensure(&h->xlist, &h->xlist_cap, (size_t)nseg * h->N * cx.xcap));
+    HIPCHK(h, ensure(&h->xcount, &h->xcount_cap, (size_t)nseg * h->N));
+    cx.xlist = h->xlist;
+    cx.xcount = h->xcount;
+    h->xcap = cx.xcap;
+    HIPCHK(h, launch_crossing_segments(cx, h->stream));
     return FT_OK;
 }
 
@@ -687,12 +713,13 @@ static ft_status run_minibatch(ft_handle *h, int64_t b, int apply,
         sa.pos[n] = h->sv[h->sort_final][n] + off;
         sa.A[n] = h->A[n];
         sa.A16[n] = h->sh.bf16 ? h->A16[n] : nullptr;
+        sa.xlist[n] = h->xlist + ((size_t)b * h->N + n) * h->xcap;
         sa.grad[n] = grad ? grad[n] : nullptr;
         sa.count[n] = count ? count[n] : nullptr;
     }
     sa.G = h->G;
-    sa.first = h->first;
-    sa.last = h->last;
+    sa.xcount = h->xcount + (size_t)b * h->N;
+    sa.xcap = h->xcap;
     sa.lr = (float)h->opt.lr_A;
     sa.lam = (float)h->opt.lambda_A;
     sa.mean = h->opt.row_scale == FT_ROW_MEAN;
@@ -701,21 +728,14 @@ static ft_status run_minibatch(ft_handle *h, int64_t b, int apply,
         LaunchExt L(h, FT_K_SEG_REDUCE);
         HIPCHK(h, launch_seg_reduce(sa, h->stream));
     }
-    {
-        LaunchExt L(h, FT_K_SEG_FIXUP);
-        HIPCHK(h, launch_seg_fixup(sa, h->stream));
-    }
     return FT_OK;
 }
 
 static ft_status alloc_factor(ft_handle *h, int64_t nmb, int nper) {
     const int64_t M = std::min<int64_t>(h->opt.minibatch, h->nnz[FT_TRAIN]);
     const int64_t nch = (M + kSegChunk - 1) / kSegChunk;
+    (void)nch;
     HIPCHK(h, ensure(&h->G, &h->G_cap, (size_t)h->N * M * h->sh.J4));
-    size_t cap_first = h->fl_cap, cap_last = h->fl_cap;
-    HIPCHK(h, ensure(&h->first, &cap_first, (size_t)h->N * nch * h->sh.J4));
-    HIPCHK(h, ensure(&h->last, &cap_last, (size_t)h->N * nch * h->sh.J4));
-    h->fl_cap = std::min(cap_first, cap_last);
     HIPCHK(h, ensure(&h->mb_part, &h->mb_part_cap, (size_t)nmb * nper));
     HIPCHK(h, ensure(&h->mb_loss, &h->mb_loss_cap, (size_t)nmb));
     return FT_OK;
@@ -893,13 +913,15 @@ static ft_status core_pass(ft_handle *h, const int32_t *const *idx,
     ca.count = count;
     ca.part = h->core_part;
     ca.loss_part = h->dpart;
+    int used = nb;
+    ca.blocks_used = &used;
     {
         LaunchExt L(h, FT_K_CORE_GRAD);
         HIPCHK(h, launch_core_grad(h->sh, ca, nb, h->stream));
     }
     CoreUpdateArgs ua{};
     ua.part = h->core_part;
-    ua.nblocks = nb;
+    ua.nblocks = used;
     for (int n = 0; n < h->N; ++n) ua.B[n] = h->B[n];
     ua.grad_out = grad_out;
     ua.inv_count = 1.0 / (double)count;
@@ -910,7 +932,7 @@ static ft_status core_pass(ft_handle *h, const int32_t *const *idx,
         LaunchExt L(h, FT_K_CORE_UPDATE);
         HIPCHK(h, launch_core_update(h->sh, ua, h->stream));
     }
-    HIPCHK(h, launch_sum_blocks(h->dpart, nb, 1, loss_dev, h->stream));
+    HIPCHK(h, launch_sum_blocks(h->dpart, used, 1, loss_dev, h->stream));
     return FT_OK;
 }
 
@@ -1146,8 +1168,9 @@ extern "C" ft_status ft_profile_get(ft_handle *h, int32_t kernel,
 // ------------------------------------------------------------------ stateless
 namespace {
 struct MbLayout {
-    size_t bpad, G, sk0, sk1, sv0, sv1, counts, first, last, ordinal,
+    size_t bpad, G, sk0, sk1, sv0, sv1, counts, xlist, xcount, ordinal,
         tile_count, total, core_part, dpart, bytes;
+    int xcap;
     int tps, nch, ntiles_scan, nb_core, nb_fact, nb_eval;
     Shape sh;
 };
@@ -1200,8 +1223,9 @@ MbLayout mb_layout(const ft_problem_desc *p, int64_t m) {
     L.sv0 = take(sizeof(uint32_t) * N * m);
     L.sv1 = take(sizeof(uint32_t) * N * m);
     L.counts = take(sizeof(uint32_t) * N * kRadix * L.tps);
-    L.first = take(sizeof(float) * N * L.nch * J4);
-    L.last = take(sizeof(float) * N * L.nch * J4);
+    L.xcap = cross_capacity(m);
+    L.xlist = take(sizeof(int2) * N * L.xcap);
+    L.xcount = take(sizeof(int32_t) * N);
     L.ordinal = take(sizeof(uint32_t) * N * m);
     L.tile_count = take(sizeof(uint32_t) * N * L.ntiles_scan);
     L.total = take(sizeof(int64_t) * N);
@@ -1368,10 +1392,23 @@ extern "C" ft_status ft_mb_backward(
     sa.m = (int32_t)m;
     sa.nchunks = L.nch;
     sa.G = fa.G;
-    sa.first = at<float>(workspace, L.first);
-    sa.last = at<float>(workspace, L.last);
     sa.apply = 2;
     sa.scale = grad_out_dev;
+    {
+        CrossArgs cx{};
+        cx.N = N;
+        cx.nnz = m;
+        cx.M = m;
+        cx.nseg = 1;
+        cx.xcap = L.xcap;
+        for (int n = 0; n < N; ++n) cx.rows[n] = sk[cur] + (size_t)n * m;
+        cx.xlist = at<int2>(workspace, L.xlist);
+        cx.xcount = at<int32_t>(workspace, L.xcount);
+        HIPCHK0(launch_crossing_segments(cx, s));
+        sa.xcount = cx.xcount;
+        sa.xcap = L.xcap;
+        for (int n = 0; n < N; ++n) sa.xlist[n] = cx.xlist + (size_t)n * L.xcap;
+    }
     for (int n = 0; n < N; ++n) {
         sa.rows[n] = sk[cur] + (size_t)n * m;
         sa.pos[n] = sv[cur] + (size_t)n * m;
@@ -1397,7 +1434,6 @@ extern "C" ft_status ft_mb_backward(
         HIPCHK0(launch_unique_scan(u, s));
     }
     HIPCHK0(launch_seg_reduce(sa, s));
-    HIPCHK0(launch_seg_fixup(sa, s));
 
     // core gradients over the minibatch
     CoreArgs ca{};
@@ -1410,10 +1446,12 @@ extern "C" ft_status ft_mb_backward(
     ca.count = m;
     ca.part = at<float>(workspace, L.core_part);
     ca.loss_part = at<double>(workspace, L.dpart);
+    int used = L.nb_core;
+    ca.blocks_used = &used;
     HIPCHK0(launch_core_grad(L.sh, ca, L.nb_core, s));
     CoreUpdateArgs ua{};
     ua.part = ca.part;
-    ua.nblocks = L.nb_core;
+    ua.nblocks = used;
     ua.apply = 0;
     ua.R = p->R;
     ua.scale = grad_out_dev;

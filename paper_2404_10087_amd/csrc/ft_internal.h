@@ -61,7 +61,12 @@ hipError_t launch_epoch_order(uint32_t *perm, int64_t n, uint64_t key,
                               hipStream_t s);
 hipError_t launch_copy_order(uint32_t *perm, const int64_t *src, int64_t n,
                              hipStream_t s);
-hipError_t launch_permute(int N, const int32_t *const *idx, const float *val,
+// Training-set records: RW = 4 words (order <= 3) or 8 words (order 4..5).
+inline int record_words(int N) { return N <= 3 ? 4 : 8; }
+hipError_t launch_pack_records(int N, const int32_t *const *idx,
+                               const float *val, int64_t nnz, uint32_t *rec,
+                               int rw, hipStream_t s);
+hipError_t launch_permute(int N, const uint32_t *rec, int rw,
                           const uint32_t *perm, int64_t nnz,
                           int32_t *const *pidx, float *pval, hipStream_t s);
 
@@ -116,8 +121,11 @@ struct SegArgs {
     const uint32_t *pos[kMaxOrder];   // sorted in-minibatch positions
     const float *G;                   // [N][m][J4]
     float *A[kMaxOrder];
-    float *first;                     // [N][nchunks][J4]
-    float *last;                      // [N][nchunks][J4]
+    // rows whose samples cross a chunk edge: (first, end) sorted indices,
+    // xcount[n] of them for mode n (capacity xcap each)
+    const int2 *xlist[kMaxOrder];
+    const int32_t *xcount;
+    int xcap;
     float lr, lam;
     int mean;                         // FT_ROW_MEAN
     int apply;                        // 1: update A; 0: write grad/count;
@@ -134,7 +142,24 @@ struct SegArgs {
     const float *scale;
 };
 hipError_t launch_seg_reduce(const SegArgs &a, hipStream_t s);
-hipError_t launch_seg_fixup(const SegArgs &a, hipStream_t s);
+
+// Per epoch (after the sort): list every row segment of every minibatch
+// and mode that crosses a kSegChunk edge.
+struct CrossArgs {
+    int N;
+    int64_t nnz;
+    int64_t M;
+    int nseg;
+    int xcap;                         // max(1, ceil(min(M, nnz) / kSegChunk) - 1)
+    const uint32_t *rows[kMaxOrder];  // sorted rows of the whole epoch
+    int2 *xlist;                      // [nseg][N][xcap]
+    int32_t *xcount;                  // [nseg][N], zeroed by the launcher
+};
+hipError_t launch_crossing_segments(const CrossArgs &c, hipStream_t s);
+inline int cross_capacity(int64_t m) {
+    const int64_t ch = (m + kSegChunk - 1) / kSegChunk;
+    return ch > 1 ? (int)(ch - 1) : 1;
+}
 
 hipError_t launch_sum_blocks(const double *part, int nper, int ngroups,
                              double *out, hipStream_t s);
@@ -149,7 +174,10 @@ struct CoreArgs {
     const float *B[kMaxOrder];
     float *part;          // [nblocks][N][J4][R16]
     double *loss_part;    // [nblocks]
+    int *blocks_used;     // host: the grid actually launched
 };
+// Upper bound of the core-gradient grid (partial buffers are sized for it);
+// the launch may use fewer blocks (what fits on the device at once).
 int core_grad_blocks(int64_t count);
 hipError_t launch_core_grad(const Shape &sh, const CoreArgs &a, int nblocks,
                             hipStream_t s);

@@ -27,15 +27,54 @@ int core_grad_blocks(int64_t count) {
     return blocks < 1 ? 1 : (int)blocks;
 }
 
+// Per-tile inputs, loaded one tile ahead of the arithmetic.
+template <int N, int KQ, bool BF>
+struct CoreTileIn {
+    RowFrag<KQ, BF> arow[N];   // A[s = c][KQ q .. KQ q + KQ - 1]
+    float x[4];                // values of samples 4q + v
+};
+
+template <int N, int KQ, bool BF>
+__device__ __forceinline__ void load_core_tile(const CoreArgs &a, int64_t tile,
+                                               int q, int c,
+                                               CoreTileIn<N, KQ, BF> &in) {
+    constexpr int J4 = 4 * KQ;
+    const int64_t base = tile * 16;
+    const int64_t last = a.count - 1;
+    const int64_t ps = base + c <= last ? base + c : last;
+#pragma unroll
+    for (int n = 0; n < N; ++n) {
+        const int row = a.idx[n][ps];
+        in.arow[n].load(a.A[n], a.A16[n], (int64_t)row * J4 + KQ * q);
+    }
+    const int64_t s0 = base + 4 * q;
+    if (s0 + 3 <= last) {
+        const float4 xv = *reinterpret_cast<const float4 *>(a.val + s0);
+        in.x[0] = xv.x;
+        in.x[1] = xv.y;
+        in.x[2] = xv.z;
+        in.x[3] = xv.w;
+    } else {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) in.x[v] = s0 + v <= last ? a.val[s0 + v] : 0.f;
+    }
+}
+
 template <int N, int KQ, int RB, bool BF>
 __global__ __launch_bounds__(256) void core_grad_kernel(CoreArgs a,
                                                         int64_t ntiles) {
     constexpr int J4 = 4 * KQ;
     constexpr int R16 = 16 * RB;
     constexpr int JB = (KQ + 3) / 4;
-    extern __shared__ float lds[];   // [4 waves][N][J4][R16]
+    constexpr int TP = J4 + 1;       // padded row of the per-wave transpose
+    // [4 waves][N][J4][R16] partials at the end; during the sweep each wave
+    // uses [N][16][TP] of it to transpose its tile's factor rows
+    extern __shared__ float lds[];
     const int lane = threadIdx.x & 63, q = lane >> 4, c = lane & 15;
     const int wave = threadIdx.x >> 6;
+    constexpr int WAVE_LDS = (N * J4 * R16 > N * 16 * TP) ? N * J4 * R16
+                                                          : N * 16 * TP;
+    float *tr = lds + wave * WAVE_LDS;
 
     ColFrag<KQ, BF> bop[N][RB];   // B-operand: B[k = KQ*q + t][r = 16 rb + c]
 #pragma unroll
@@ -55,24 +94,22 @@ __global__ __launch_bounds__(256) void core_grad_kernel(CoreArgs a,
 
     double loss = 0.0;
     const int64_t nwaves = (int64_t)gridDim.x * 4;
-    for (int64_t tile = (int64_t)blockIdx.x * 4 + wave; tile < ntiles;
-         tile += nwaves) {
+    const int64_t last = a.count - 1;
+    int64_t tile = (int64_t)blockIdx.x * 4 + wave;
+    CoreTileIn<N, KQ, BF> nxt;
+    if (tile < ntiles) load_core_tile<N, KQ, BF>(a, tile, q, c, nxt);
+    for (; tile < ntiles; tile += nwaves) {
+        const CoreTileIn<N, KQ, BF> cur = nxt;
+        if (tile + nwaves < ntiles)
+            load_core_tile<N, KQ, BF>(a, tile + nwaves, q, c, nxt);
         const int64_t base = tile * 16;
-        const int64_t last = a.count - 1;
-        const int64_t ps = base + c <= last ? base + c : last;
 
-        RowFrag<KQ, BF> arow[N];
-#pragma unroll
-        for (int n = 0; n < N; ++n) {
-            const int row = a.idx[n][ps];
-            arow[n].load(a.A[n], a.A16[n], (int64_t)row * J4 + KQ * q);
-        }
         floatx4 C[N][RB];   // C[s = 4q + v][r = 16 rb + c]
 #pragma unroll
         for (int n = 0; n < N; ++n)
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb)
-                C[n][rb] = contract(arow[n], bop[n][rb],
+                C[n][rb] = contract(cur.arow[n], bop[n][rb],
                                     floatx4{0.f, 0.f, 0.f, 0.f});
         floatx4 D[N][RB];
 #pragma unroll
@@ -91,33 +128,34 @@ __global__ __launch_bounds__(256) void core_grad_kernel(CoreArgs a,
             }
         }
         float r[4];
-        int64_t sv[4];
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             float xh = 0.f;
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb) xh += C[0][rb][v] * D[0][rb][v];
             xh = sum_row16(xh);
-            const int64_t s = base + 4 * q + v;
-            sv[v] = s <= last ? s : last;
-            r[v] = s <= last ? xh - a.val[sv[v]] : 0.f;
-            if (c == 0 && s <= last) loss += 0.5 * (double)r[v] * (double)r[v];
+            const bool ok = base + 4 * q + v <= last;
+            r[v] = ok ? xh - cur.x[v] : 0.f;
+            if (c == 0 && ok) loss += 0.5 * (double)r[v] * (double)r[v];
         }
+        // transpose the tile's rows through LDS: lane (c, q) needs
+        // A[s = 4q + v][j = 16 jb + c] for the contraction over samples
+        wave_lds_sync();
+#pragma unroll
+        for (int n = 0; n < N; ++n)
+#pragma unroll
+            for (int t = 0; t < KQ; ++t)
+                tr[(n * 16 + c) * TP + KQ * q + t] = cur.arow[n].value(t);
+        wave_lds_sync();
 #pragma unroll
         for (int n = 0; n < N; ++n) {
-            int rows4[4];
-#pragma unroll
-            for (int v = 0; v < 4; ++v) rows4[v] = a.idx[n][sv[v]];
 #pragma unroll
             for (int jb = 0; jb < JB; ++jb) {
                 const int j = 16 * jb + c;
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
-                    float av = 0.f;
-                    if (j < J4) {
-                        const int64_t o = (int64_t)rows4[v] * J4 + j;
-                        av = BF ? bf2f(a.A16[n][o]) : a.A[n][o];
-                    }
+                    const float av =
+                        j < J4 ? tr[(n * 16 + 4 * q + v) * TP + j] : 0.f;
                     const float e = r[v] * av;
 #pragma unroll
                     for (int rb = 0; rb < RB; ++rb)
@@ -127,6 +165,8 @@ __global__ __launch_bounds__(256) void core_grad_kernel(CoreArgs a,
             }
         }
     }
+    wave_lds_sync();
+    __syncthreads();
 
     // grad[n][jb][rb][v] holds Grad^(n)[j = 16 jb + 4q + v][r = 16 rb + c]
     float *mine = lds + wave * (N * J4 * R16);
@@ -152,10 +192,36 @@ __global__ __launch_bounds__(256) void core_grad_kernel(CoreArgs a,
     if (threadIdx.x == 0) a.loss_part[blockIdx.x] = tot;
 }
 
+// Persistent grid: as many blocks as fit on the device at once (never more
+// than one per four tiles); the tile-to-wave assignment, and with it the
+// summation order, depends only on this number.
+static int resident_blocks(const void *kernel, size_t lds) {
+    static int ncu = 0;
+    if (ncu == 0) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount,
+                                  dev) != hipSuccess || ncu < 1)
+            ncu = 256;
+    }
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 256,
+                                                     lds) != hipSuccess ||
+        per_cu < 1)
+        per_cu = 1;
+    return ncu * per_cu;
+}
+
 template <int N, int KQ, int RB, bool BF>
 static hipError_t launch_cg(const CoreArgs &a, int blocks, hipStream_t s) {
     const int64_t ntiles = (a.count + 15) / 16;
-    const size_t lds = sizeof(float) * 4 * N * (4 * KQ) * (16 * RB);
+    const int part = N * (4 * KQ) * (16 * RB);
+    const int trans = N * 16 * (4 * KQ + 1);
+    const size_t lds = sizeof(float) * 4 * (part > trans ? part : trans);
+    const int fit = resident_blocks(
+        reinterpret_cast<const void *>(&core_grad_kernel<N, KQ, RB, BF>), lds);
+    if (blocks > fit) blocks = fit;
+    *a.blocks_used = blocks;
     FT_LAUNCH((core_grad_kernel<N, KQ, RB, BF>), dim3(blocks),
                        dim3(256), lds, s, a, ntiles);
     return hipGetLastError();
@@ -189,6 +255,7 @@ static hipError_t launch_cg_j(const Shape &sh, const CoreArgs &a, int blocks,
 
 hipError_t launch_core_grad(const Shape &sh, const CoreArgs &a, int nblocks,
                             hipStream_t s) {
+    if (nblocks > kCoreMaxBlocks) nblocks = kCoreMaxBlocks;
     switch (sh.N) {
     case 2: return launch_cg_j<2>(sh, a, nblocks, s);
     case 3: return launch_cg_j<3>(sh, a, nblocks, s);

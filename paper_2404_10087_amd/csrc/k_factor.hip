@@ -12,13 +12,12 @@
 // natural "sample-column" layout so it is stored as float4 rows with no
 // transpose. All reads use A and B as they stand at the minibatch start.
 //
-// seg_reduce_kernel / seg_fixup_kernel: the deterministic row reduction.
-// The builder has sorted every minibatch's samples by row (ties in minibatch
-// order). A wave takes a fixed chunk of kSegChunk sorted samples, one per
-// lane, and sums each row's gradients by a segmented scan across its lanes;
-// rows whose samples all lie in the chunk are finished there, the fragment
-// sums of rows that cross a chunk edge are combined by the fix-up kernel in
-// a fixed order. A finished row takes
+// seg_reduce_kernel: the deterministic row reduction. The builder has sorted
+// every minibatch's samples by row (ties in minibatch order) and listed the
+// rows whose samples cross a chunk edge. A wave takes a fixed chunk of
+// kSegChunk sorted samples, one per lane, and sums each row's gradients by a
+// segmented scan across its lanes; every listed crossing row gets a block of
+// its own. A finished row takes
 //     G = sum_s g_s + k * lambda_A * a,   a <- a - lr_A * G   (or G / k)
 // No floating-point atomics are used, so results are bitwise reproducible.
 #include "ft_internal.h"
@@ -339,16 +338,54 @@ __device__ __forceinline__ void finish_row(const SegArgs &a, int n,
     }
 }
 
-// One wave per chunk of 64 sorted samples of one mode; lane l holds sample
-// i0 + l with its whole gradient row. A segmented inclusive scan across the
-// lanes (Hillis-Steele, steps 1..32, a lane adds the value d lanes below when
-// that lane belongs to its segment) leaves every row's chunk-local sum in
-// the lane of its last sample; that lane finishes the row if all of its
-// samples are in the chunk, or stores the fragment sum for the fix-up. The
-// addition tree depends only on the data, so results are reproducible.
+// Chunk part (blocks [0, chunk_blocks)): one wave per chunk of 64 sorted
+// samples of one mode; lane l holds sample i0 + l with its whole gradient
+// row. A segmented inclusive scan across the lanes (Hillis-Steele, steps
+// 1..32; a lane adds the value d lanes below when that lane belongs to its
+// segment) leaves every row's sum in the lane of its last sample, which
+// finishes the row -- unless the row's samples cross a chunk edge.
+// Crossing part (the remaining blocks): one 256-thread block per crossing
+// row, from the builder's list; thread t sums samples t, t+256, ... and a
+// fixed LDS tree adds the 256 partial rows. No block depends on another and
+// every addition order is fixed by the data, so results are reproducible.
 template <int KQ>
-__global__ __launch_bounds__(256) void seg_reduce_kernel(SegArgs a) {
+__global__ __launch_bounds__(256) void seg_reduce_kernel(SegArgs a,
+                                                         int chunk_blocks) {
     constexpr int J4 = 4 * KQ;
+    __shared__ float red[256][J4 + 1];
+    if ((int)blockIdx.x >= chunk_blocks) {
+        const int j = blockIdx.x - chunk_blocks;
+        const int n = j / a.xcap, e = j % a.xcap;
+        if (e >= a.xcount[n]) return;             // uniform per block
+        const int2 se = a.xlist[n][e];
+        const int t = threadIdx.x;
+        float acc[J4];
+#pragma unroll
+        for (int q = 0; q < J4; ++q) acc[q] = 0.f;
+        const float *G = a.G + (int64_t)n * a.m * J4;
+        for (int i = se.x + t; i < se.y; i += 256) {
+            float g[J4];
+            load_row_part<J4>(G + (int64_t)a.pos[n][i] * J4, g);
+#pragma unroll
+            for (int q = 0; q < J4; ++q) acc[q] += g[q];
+        }
+#pragma unroll
+        for (int q = 0; q < J4; ++q) red[t][q] = acc[q];
+        __syncthreads();
+        for (int stride = 128; stride >= 1; stride >>= 1) {
+            if (t < stride)
+#pragma unroll
+                for (int q = 0; q < J4; ++q) red[t][q] += red[t + stride][q];
+            __syncthreads();
+        }
+        if (t == 0) {
+            float g[J4];
+#pragma unroll
+            for (int q = 0; q < J4; ++q) g[q] = red[0][q];
+            finish_row<J4>(a, n, a.rows[n][se.x], g, se.y - se.x, se.x);
+        }
+        return;
+    }
     const int lane = threadIdx.x & 63;
     const int gw = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (gw >= a.N * a.nchunks) return;           // uniform per wave
@@ -386,100 +423,33 @@ __global__ __launch_bounds__(256) void seg_reduce_kernel(SegArgs a) {
     const bool last_in_chunk = i == i1 - 1;
     const bool tail = valid && (last_in_chunk || above != row);
     if (!tail) return;
-    const bool first_frag = s == 0;
-    const bool starts_before = first_frag && i0 > 0 && rows[i0 - 1] == row;
+    const bool starts_before = s == 0 && i0 > 0 && rows[i0 - 1] == row;
     const bool continues_after = last_in_chunk && i1 < a.m && rows[i1] == row;
-    if (!starts_before && !continues_after) {
+    if (!starts_before && !continues_after)
         finish_row<J4>(a, n, row, g, lane - s + 1, i0 + s);
-        return;
-    }
-    const int64_t slot = ((int64_t)n * a.nchunks + c) * J4;
-    if (first_frag) store_row<J4>(a.first + slot, g);
-    if (last_in_chunk) store_row<J4>(a.last + slot, g);
-}
-
-// One wave per chunk: if the chunk's first sample belongs to a row that
-// started in an earlier chunk and ends in this one, sum the row's fragment
-// sums (last fragment of its first chunk, whole middle chunks, first fragment
-// of this chunk) with 64 lanes at a time and a fixed reduction tree.
-template <int KQ>
-__global__ __launch_bounds__(256) void seg_fixup_kernel(SegArgs a) {
-    constexpr int J4 = 4 * KQ;
-    const int lane = threadIdx.x & 63;
-    const int gw = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (gw >= a.N * a.nchunks) return;
-    const int n = gw / a.nchunks, c = gw % a.nchunks;
-    const int i0 = c * kSegChunk;
-    if (i0 == 0) return;
-    const uint32_t *rows = a.rows[n];
-    const uint32_t row = rows[i0];
-    if (rows[i0 - 1] != row) return;              // row starts in this chunk
-    const int i1 = min(i0 + kSegChunk, a.m);
-    if (i1 < a.m && rows[i1 - 1] == row && rows[i1] == row)
-        return;                                   // row ends after this chunk
-    int lo = 0, hi = i0;                          // first sorted index of row
-    while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (rows[mid] < row) lo = mid + 1; else hi = mid;
-    }
-    const int start = lo;
-    const bool same = i0 + lane < i1 && rows[i0 + lane] == row;
-    const int end = i0 + __popcll(__ballot(same));
-    const int c0 = start / kSegChunk;
-    const int nparts = c - c0 + 1;
-    float g[J4];
-#pragma unroll
-    for (int j = 0; j < J4; ++j) g[j] = 0.f;
-    for (int k = lane; k < nparts; k += 64) {
-        const int cc = c0 + k;
-        const float *src = (k == 0 ? a.last : a.first) +
-                           ((int64_t)n * a.nchunks + cc) * J4;
-        float t[J4];
-        load_row_part<J4>(src, t);
-#pragma unroll
-        for (int j = 0; j < J4; ++j) g[j] += t[j];
-    }
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1)
-#pragma unroll
-        for (int j = 0; j < J4; ++j) g[j] += __shfl_xor(g[j], d);
-    if (lane == 0) finish_row<J4>(a, n, row, g, end - start, start);
 }
 
 template <int KQ>
-static hipError_t launch_seg_pair(const SegArgs &a, bool fixup,
-                                  hipStream_t s) {
-    const int waves = a.N * a.nchunks;
-    const int blocks = (waves + 3) / 4;
-    if (fixup)
-        FT_LAUNCH(seg_fixup_kernel<KQ>, dim3(blocks), dim3(256), 0, s,
-                           a);
-    else
-        FT_LAUNCH(seg_reduce_kernel<KQ>, dim3(blocks), dim3(256), 0,
-                           s, a);
+static hipError_t launch_seg_kq(const SegArgs &a, hipStream_t s) {
+    const int chunk_blocks = (a.N * a.nchunks + 3) / 4;
+    const int blocks = chunk_blocks + a.N * a.xcap;
+    FT_LAUNCH(seg_reduce_kernel<KQ>, dim3(blocks), dim3(256), 0, s, a,
+              chunk_blocks);
     return hipGetLastError();
 }
 
-static hipError_t launch_seg(const SegArgs &a, bool fixup, hipStream_t s) {
+hipError_t launch_seg_reduce(const SegArgs &a, hipStream_t s) {
     switch (a.J4) {
-    case 4: return launch_seg_pair<1>(a, fixup, s);
-    case 8: return launch_seg_pair<2>(a, fixup, s);
-    case 12: return launch_seg_pair<3>(a, fixup, s);
-    case 16: return launch_seg_pair<4>(a, fixup, s);
-    case 20: return launch_seg_pair<5>(a, fixup, s);
-    case 24: return launch_seg_pair<6>(a, fixup, s);
-    case 28: return launch_seg_pair<7>(a, fixup, s);
-    case 32: return launch_seg_pair<8>(a, fixup, s);
+    case 4: return launch_seg_kq<1>(a, s);
+    case 8: return launch_seg_kq<2>(a, s);
+    case 12: return launch_seg_kq<3>(a, s);
+    case 16: return launch_seg_kq<4>(a, s);
+    case 20: return launch_seg_kq<5>(a, s);
+    case 24: return launch_seg_kq<6>(a, s);
+    case 28: return launch_seg_kq<7>(a, s);
+    case 32: return launch_seg_kq<8>(a, s);
     }
     return hipErrorInvalidValue;
-}
-
-hipError_t launch_seg_reduce(const SegArgs &a, hipStream_t s) {
-    return launch_seg(a, false, s);
-}
-
-hipError_t launch_seg_fixup(const SegArgs &a, hipStream_t s) {
-    return launch_seg(a, true, s);
 }
 
 // ------------------------------------------------------------ block sums

@@ -55,6 +55,7 @@ struct RowFrag<KQ, false> {
         load_row(A + off);
     }
     __device__ __forceinline__ void load_row(const float *p);
+    __device__ __forceinline__ float value(int t) const { return v[t]; }
 };
 
 template <int KQ>
@@ -75,6 +76,9 @@ struct RowFrag<KQ, true> {
                 for (int e = 0; e < 4; ++e)
                     v[u][e] = 4 * u + e < KQ ? (short)p[4 * u + e] : (short)0;
         }
+    }
+    __device__ __forceinline__ float value(int t) const {
+        return bf2f((uint16_t)v[t / 4][t % 4]);
     }
 };
 
@@ -202,6 +206,14 @@ __device__ __forceinline__ float sum_row16(float x) {
     x += __shfl_xor(x, 4);
     x += __shfl_xor(x, 8);
     return x;
+}
+
+// Order the LDS traffic of one wave (its lanes exchange data through LDS
+// without a workgroup barrier).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 __device__ __forceinline__ double wave_sum(double x) {

@@ -368,3 +368,16 @@ def test_loss_and_residual_stats_definitions(oracle_mod):
            + lamB * sum((b * b).sum() for b in B))
     assert oracle_mod.loss(A, B, idx, vals, lamA, lamB) == pytest.approx(
         ref, rel=1e-12)
+
+
+def test_core_epoch_step_matches_autograd(oracle_mod):
+    """Algorithm 5: B <- B - lr (Grad / |Omega| + lambda B), with Grad the
+    autograd gradient of sum r^2/2 over the set (all modes at once)."""
+    A, B, idx, vals = rand_problem((7, 6, 5), (3, 2, 4), 3, 90, 31)
+    lr, lam = 0.3, 0.05
+    _, gB, _ = torch_minibatch_grads(A, B, idx, vals, 0.0)
+    B1 = [b.copy() for b in B]
+    oracle_mod.core_epoch(A, B1, idx, vals, lr, lam)
+    for n in range(3):
+        np.testing.assert_allclose(B1[n], B[n] - lr * (gB[n] / 90 + lam * B[n]),
+                                   rtol=1e-11, atol=1e-13)

@@ -225,7 +225,9 @@ typedef struct {
 } ft_problem_desc;
 
 /* Bytes of device workspace that ft_mb_forward / ft_mb_backward need for a
- * minibatch of m samples (1 <= m <= 2^30). */
+ * minibatch of m samples (1 <= m <= 2^30). The workspace must be 256-byte
+ * aligned and every A[n] 16-byte aligned (FT_EINVAL otherwise); device
+ * allocations are. */
 ft_status ft_mb_workspace_size(const ft_problem_desc *p, int64_t m,
                                size_t *bytes);
 

@@ -74,6 +74,7 @@ struct ft_handle {
     int32_t *xcount = nullptr;
     size_t xcount_cap = 0;
     int xcap = 1;
+    std::vector<int32_t> xcount_host;  // crossing rows per minibatch and mode
     double *mb_part = nullptr;
     size_t mb_part_cap = 0;
     double *mb_loss = nullptr;
@@ -661,6 +662,13 @@ static ft_status build_minibatches(ft_handle *h) {
     cx.xcount = h->xcount;
     h->xcap = cx.xcap;
     HIPCHK(h, launch_crossing_segments(cx, h->stream));
+    // the crossing-row counts size the reduction grids: one read-back per
+    // epoch instead of a worst-case grid per minibatch
+    h->xcount_host.resize((size_t)nseg * h->N);
+    HIPCHK(h, hipMemcpyAsync(h->xcount_host.data(), h->xcount,
+                             sizeof(int32_t) * nseg * h->N,
+                             hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
     return FT_OK;
 }
 
@@ -720,6 +728,8 @@ static ft_status run_minibatch(ft_handle *h, int64_t b, int apply,
     sa.G = h->G;
     sa.xcount = h->xcount + (size_t)b * h->N;
     sa.xcap = h->xcap;
+    sa.ncross = 0;
+    for (int n = 0; n < h->N; ++n) sa.ncross += h->xcount_host[b * h->N + n];
     sa.lr = (float)h->opt.lr_A;
     sa.lam = (float)h->opt.lambda_A;
     sa.mean = h->opt.row_scale == FT_ROW_MEAN;
@@ -1274,10 +1284,15 @@ static ft_status check_mb_args(const ft_problem_desc *p, const float *const *A,
     if (st != FT_OK) return st;
     if (!A || !B || !idx || !val || !ws)
         return fail(nullptr, FT_EINVAL, "A, B, idx, val or workspace is NULL");
-    for (int n = 0; n < p->order; ++n)
+    for (int n = 0; n < p->order; ++n) {
         if (!A[n] || !B[n] || !idx[n])
             return fail(nullptr, FT_EINVAL, "A[%d], B[%d] or idx[%d] is NULL",
                         n, n, n);
+        if (reinterpret_cast<uintptr_t>(A[n]) % 16)
+            return fail(nullptr, FT_EINVAL, "A[%d] is not 16-byte aligned", n);
+    }
+    if (reinterpret_cast<uintptr_t>(ws) % 256)
+        return fail(nullptr, FT_EINVAL, "workspace is not 256-byte aligned");
     const size_t need = mb_layout(p, m).bytes;
     if (ws_bytes < need)
         return fail(nullptr, FT_EINVAL, "workspace of %zu bytes < %zu needed",
@@ -1407,6 +1422,7 @@ extern "C" ft_status ft_mb_backward(
         HIPCHK0(launch_crossing_segments(cx, s));
         sa.xcount = cx.xcount;
         sa.xcap = L.xcap;
+        sa.ncross = N * L.xcap;        // worst case; surplus blocks exit
         for (int n = 0; n < N; ++n) sa.xlist[n] = cx.xlist + (size_t)n * L.xcap;
     }
     for (int n = 0; n < N; ++n) {

@@ -81,7 +81,7 @@ struct SortPass {
     const uint32_t *val_in[kMaxOrder];   // nullptr: payload = position in segment
     uint32_t *key_out[kMaxOrder];
     uint32_t *val_out[kMaxOrder];
-    uint32_t *counts;    // [N][nseg][kRadix][tiles_per_seg]
+    uint32_t *counts;    // [N][nseg][tiles_per_seg][kRadix]
 };
 hipError_t launch_sort_pass(const SortPass &p, hipStream_t s);
 
@@ -126,6 +126,7 @@ struct SegArgs {
     const int2 *xlist[kMaxOrder];
     const int32_t *xcount;
     int xcap;
+    int ncross;                       // sum of xcount over the modes (host)
     float lr, lam;
     int mean;                         // FT_ROW_MEAN
     int apply;                        // 1: update A; 0: write grad/count;

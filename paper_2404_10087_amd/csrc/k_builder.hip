@@ -15,38 +15,54 @@
 namespace ft {
 
 // ------------------------------------------------------------------ order
-// Counter-based permutation of [0, n): a 4-round balanced Feistel network on
-// 2h bits (Luby-Rackoff) whose round function is the SplitMix64 finaliser
-// (Steele, Lea & Flood, 2014), restricted to [0, n) by cycle walking (Black &
-// Rogaway, 2002). Round keys are consecutive SplitMix64 outputs from `key`.
-__device__ __forceinline__ uint64_t mix64(uint64_t z) {
-    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
-    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
-    return z ^ (z >> 31);
+// Counter-based permutation of [0, n): a 4-round Feistel network on the
+// mixed-radix domain Z_a x Z_b with a = ceil(sqrt n), b = ceil(n / a)
+// (Black & Rogaway, 2002, generalised Feistel): x = L b + R; a round maps
+// (L in Z_p, R in Z_q) to (R, (L + F_i(R)) mod p), so the halves swap moduli
+// and after four rounds the pair is back in Z_a x Z_b. F_i(R) is the
+// MurmurHash3 32-bit finaliser (Appleby) of R ^ k_i, scaled into [0, p) by a
+// 32x32 -> 64-bit product. Values in [n, ab) are cycle-walked; since
+// ab - n < a the walk almost never runs, so the lanes of a wave stay
+// converged. Round keys are the high halves of consecutive SplitMix64
+// outputs (Steele, Lea & Flood, 2014) from `key`. All arithmetic is 32-bit.
+__device__ __forceinline__ uint32_t fmix32(uint32_t h) {
+    h ^= h >> 16;
+    h *= 0x85ebca6bu;
+    h ^= h >> 13;
+    h *= 0xc2b2ae35u;
+    h ^= h >> 16;
+    return h;
 }
 
 struct Feistel {
-    uint64_t k[4];
-    int h;
-    uint64_t mask;
+    uint32_t k[4];
+    uint32_t a, b;
 };
 
-__global__ void epoch_order_kernel(uint32_t *perm, int64_t n, Feistel f) {
-    int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n;
-         p += stride) {
-        uint64_t x = (uint64_t)p;
-        do {
-            uint64_t L = x >> f.h, R = x & f.mask;
+__device__ __forceinline__ uint32_t feistel_enc(uint32_t x, const Feistel &f) {
+    uint32_t L = x / f.b, R = x - L * f.b;
+    uint32_t p = f.a, q = f.b;            // L in Z_p, R in Z_q
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                uint64_t t = L ^ (mix64(R ^ f.k[i]) & f.mask);
-                L = R;
-                R = t;
-            }
-            x = (L << f.h) | R;
-        } while (x >= (uint64_t)n);
-        perm[p] = (uint32_t)x;
+    for (int i = 0; i < 4; ++i) {
+        const uint32_t fr = __umulhi(fmix32(R ^ f.k[i]), p);
+        uint32_t t = L + fr;
+        if (t >= p) t -= p;
+        L = R;
+        R = t;
+        const uint32_t s = p;
+        p = q;
+        q = s;
+    }
+    return L * f.b + R;
+}
+
+__global__ void epoch_order_kernel(uint32_t *perm, uint32_t n, Feistel f) {
+    const uint32_t stride = gridDim.x * blockDim.x;
+    for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < n;
+         p += stride) {
+        uint32_t x = feistel_enc(p, f);
+        while (x >= n) x = feistel_enc(x, f);
+        perm[p] = x;
     }
 }
 
@@ -58,21 +74,21 @@ static uint64_t host_mix64(uint64_t z) {
 
 hipError_t launch_epoch_order(uint32_t *perm, int64_t n, uint64_t key,
                               hipStream_t s) {
+    if (n < 1 || n > 0x7fffffffll) return hipErrorInvalidValue;
     Feistel f;
     uint64_t st = key;
     for (int i = 0; i < 4; ++i) {
         st += 0x9e3779b97f4a7c15ull;
-        f.k[i] = host_mix64(st);
+        f.k[i] = (uint32_t)(host_mix64(st) >> 32);
     }
-    int bits = 2;
-    while ((1ll << bits) < n) ++bits;
-    if (bits & 1) ++bits;
-    f.h = bits / 2;
-    f.mask = (1ull << f.h) - 1;
+    uint64_t a = 1;
+    while (a * a < (uint64_t)n) ++a;
+    f.a = (uint32_t)a;
+    f.b = (uint32_t)((n + a - 1) / a);
     int blocks = (int)((n + 255) / 256);
-    if (blocks > 4096) blocks = 4096;
+    if (blocks > 8192) blocks = 8192;
     hipLaunchKernelGGL(epoch_order_kernel, dim3(blocks), dim3(256), 0, s, perm,
-                       n, f);
+                       (uint32_t)n, f);
     return hipGetLastError();
 }
 
@@ -218,55 +234,46 @@ __device__ __forceinline__ TileInfo tile_info(const SortPass &p, int b,
     return t;
 }
 
+// counts of tile tb of segment b, mode n: kRadix consecutive words
 __device__ __forceinline__ uint32_t *counts_at(const SortPass &p, int n, int b,
-                                               int d) {
-    return p.counts +
-           (((int64_t)n * p.nseg + b) * kRadix + d) * p.tiles_per_seg;
+                                               int tb) {
+    return p.counts + (((int64_t)n * p.nseg + b) * p.tiles_per_seg + tb) *
+                          kRadix;
 }
 
-// grid: (tiles_per_seg, nseg, N)
+// grid: (tiles_per_seg, nseg, N). Digit histogram of one tile; every wave
+// counts into its own LDS histogram so hot rows contend only within a wave.
 __global__ __launch_bounds__(kSortThreads) void sort_upsweep_kernel(SortPass p) {
     const int tb = blockIdx.x, b = blockIdx.y, n = blockIdx.z;
     TileInfo t = tile_info(p, b, tb);
     if (t.tile_len == 0) return;
-    __shared__ uint32_t hist[kRadix];
-    hist[threadIdx.x] = 0;
+    constexpr int W = kSortThreads / 64;
+    __shared__ uint32_t hist[W][kRadix];
+    for (int w = 0; w < W; ++w) hist[w][threadIdx.x] = 0;
     __syncthreads();
     const uint32_t *keys = p.key_in[n] + t.seg_start + t.tile_off;
-    for (int i = threadIdx.x; i < t.tile_len; i += kSortThreads)
-        atomicAdd(&hist[(keys[i] >> p.shift) & (kRadix - 1)], 1u);
+    uint32_t *mine = hist[threadIdx.x >> 6];
+    uint32_t k[kSortRounds];
+#pragma unroll
+    for (int r = 0; r < kSortRounds; ++r) {
+        const int i = r * kSortThreads + threadIdx.x;
+        k[r] = i < t.tile_len ? keys[i] : 0u;
+    }
+#pragma unroll
+    for (int r = 0; r < kSortRounds; ++r)
+        if (r * kSortThreads + (int)threadIdx.x < t.tile_len)
+            atomicAdd(&mine[(k[r] >> p.shift) & (kRadix - 1)], 1u);
     __syncthreads();
-    counts_at(p, n, b, threadIdx.x)[tb] = hist[threadIdx.x];
+    uint32_t c = 0;
+    for (int w = 0; w < W; ++w) c += hist[w][threadIdx.x];
+    counts_at(p, n, b, tb)[threadIdx.x] = c;
 }
 
-// grid: (nseg, N). Exclusive scan of a segment's counts in (digit, tile)
-// order: the start of every (digit, tile) run in the sorted segment.
-__global__ __launch_bounds__(kSortThreads) void sort_scan_kernel(SortPass p) {
-    const int b = blockIdx.x, n = blockIdx.y, d = threadIdx.x;
-    TileInfo t = tile_info(p, b, 0);
-    uint32_t *c = counts_at(p, n, b, d);
-    uint32_t total = 0;
-    for (int tb = 0; tb < t.tiles_in_seg; ++tb) total += c[tb];
-    __shared__ uint32_t s[kRadix];
-    s[d] = total;
-    __syncthreads();
-    // Hillis-Steele inclusive scan over the 256 digit totals
-    for (int off = 1; off < kRadix; off <<= 1) {
-        uint32_t v = d >= off ? s[d - off] : 0u;
-        __syncthreads();
-        s[d] += v;
-        __syncthreads();
-    }
-    uint32_t run = s[d] - total;
-    for (int tb = 0; tb < t.tiles_in_seg; ++tb) {
-        uint32_t k = c[tb];
-        c[tb] = run;
-        run += k;
-    }
-}
-
-// grid: (tiles_per_seg, nseg, N). Stable scatter, staged in LDS: the tile is
-// first ordered by digit locally (the rank of an element among equal digits
+// grid: (tiles_per_seg, nseg, N). Stable scatter, staged in LDS. The global
+// start of digit d for this tile is the exclusive scan over digits of the
+// segment's digit totals plus the counts of d in the tiles before this one
+// (read from the upsweep's histograms). The tile is then ordered by digit
+// locally (the rank of an element among equal digits
 // is the number of equal digits before it in the tile, taken round by round
 // -- 256 consecutive elements per round -- from wave match masks and per-wave
 // counts), then written out so that consecutive threads store consecutive
@@ -291,7 +298,35 @@ __global__ __launch_bounds__(kSortThreads) void sort_downsweep_kernel(
     uint32_t *vout = p.val_out[n] + t.seg_start;
 
     uint32_t key[kSortRounds], val[kSortRounds];
-    base[tid] = counts_at(p, n, b, tid)[tb];
+    {
+        uint32_t before = 0, total = 0;
+        const uint32_t *c = counts_at(p, n, b, 0) + tid;
+        int k = 0;
+        for (; k + 8 <= t.tiles_in_seg; k += 8) {
+            uint32_t v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = c[(int64_t)(k + u) * kRadix];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                total += v[u];
+                before += k + u < tb ? v[u] : 0u;
+            }
+        }
+        for (; k < t.tiles_in_seg; ++k) {
+            const uint32_t v = c[(int64_t)k * kRadix];
+            total += v;
+            before += k < tb ? v : 0u;
+        }
+        lstart[tid] = total;
+        __syncthreads();
+        for (int off = 1; off < kRadix; off <<= 1) {
+            const uint32_t v = tid >= off ? lstart[tid - off] : 0u;
+            __syncthreads();
+            lstart[tid] += v;
+            __syncthreads();
+        }
+        base[tid] = lstart[tid] - total + before;
+    }
     run[tid] = 0;
     __syncthreads();
 #pragma unroll
@@ -358,8 +393,10 @@ __global__ __launch_bounds__(kSortThreads) void sort_downsweep_kernel(
 
 // ------------------------------------------------------------------ crossings
 // One thread per chunk edge q = k * kSegChunk (k >= 1) of every minibatch and
-// mode: if the row at q also occupies q - 1 and q is the first edge its
-// segment crosses, record (first, end) of the segment. The list order is
+// mode: if the row at q also occupies q - 1 and its first sample lies in the
+// chunk just before q (so q is the first edge the row crosses), record the
+// row's (first, end) sorted indices. The first sample is found in that
+// 64-entry chunk, the end by a galloping search. The list order is
 // arbitrary; every entry is reduced independently.
 __global__ void crossing_segments_kernel(CrossArgs c) {
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -376,18 +413,23 @@ __global__ void crossing_segments_kernel(CrossArgs c) {
     const uint32_t *r = c.rows[n] + off;
     const uint32_t row = r[q];
     if (r[q - 1] != row) return;
-    int lo = 0, hi = q;
+    if (q > kSegChunk && r[q - kSegChunk - 1] == row) return;  // crossed earlier
+    int lo = q - kSegChunk, hi = q;               // first index of row
     while (lo < hi) {
         const int mid = (lo + hi) >> 1;
         if (r[mid] < row) lo = mid + 1; else hi = mid;
     }
     const int first = lo;
-    if ((first / kSegChunk + 1) * kSegChunk != q) return;
-    lo = q;
-    hi = m;
+    int step = kSegChunk, probe = q;              // end: gallop, then bisect
+    while (probe + step < m && r[probe + step] == row) {
+        probe += step;
+        step <<= 1;
+    }
+    lo = probe + 1;
+    hi = probe + step < m ? probe + step : m;
     while (lo < hi) {
         const int mid = (lo + hi) >> 1;
-        if (r[mid] <= row) lo = mid + 1; else hi = mid;
+        if (r[mid] == row) lo = mid + 1; else hi = mid;
     }
     const int slot = atomicAdd(&c.xcount[b * c.N + n], 1);
     c.xlist[((int64_t)b * c.N + n) * c.xcap + slot] = make_int2(first, lo);
@@ -409,10 +451,6 @@ hipError_t launch_sort_pass(const SortPass &p, hipStream_t s) {
     dim3 g3(p.tiles_per_seg, p.nseg, p.N);
     hipLaunchKernelGGL(sort_upsweep_kernel, g3, dim3(kSortThreads), 0, s, p);
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(sort_scan_kernel, dim3(p.nseg, p.N), dim3(kSortThreads),
-                       0, s, p);
-    e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(sort_downsweep_kernel, g3, dim3(kSortThreads), 0, s, p);
     return hipGetLastError();

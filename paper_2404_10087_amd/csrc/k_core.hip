@@ -60,9 +60,20 @@ __device__ __forceinline__ void load_core_tile(const CoreArgs &a, int64_t tile,
     }
 }
 
+// Waves per SIMD the register allocator is held to: four where the tile fits
+// in 128 registers without spilling (checked per shape at build time), else
+// the compiler's choice.
+constexpr int core_waves(int N, int KQ, int RB) {
+    return (KQ * RB <= 4 &&
+            (N <= 3 || (RB == 1 && (N == 4 ? KQ <= 3 : KQ <= 1))))
+               ? 4
+               : 1;
+}
+
 template <int N, int KQ, int RB, bool BF>
-__global__ __launch_bounds__(256) void core_grad_kernel(CoreArgs a,
-                                                        int64_t ntiles) {
+__global__ __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(core_waves(N, KQ, RB)))) void
+core_grad_kernel(CoreArgs a, int64_t ntiles) {
     constexpr int J4 = 4 * KQ;
     constexpr int R16 = 16 * RB;
     constexpr int JB = (KQ + 3) / 4;

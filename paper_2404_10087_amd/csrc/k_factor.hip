@@ -27,10 +27,12 @@ namespace ft {
 
 constexpr int kFactorThreads = 256;
 constexpr int kFactorMaxBlocks = 2048;
+constexpr int kFactorTilesPerWave = 1;
 
 int factor_grad_blocks(int32_t m) {
     int ntiles = (m + 15) / 16;
-    int blocks = (ntiles + 3) / 4;
+    int blocks = (ntiles + 4 * kFactorTilesPerWave - 1) /
+                 (4 * kFactorTilesPerWave);
     if (blocks > kFactorMaxBlocks) blocks = kFactorMaxBlocks;
     return blocks < 1 ? 1 : blocks;
 }
@@ -71,19 +73,32 @@ struct FactorTile {
         }
     }
 
-    // Sample ps (this lane's column): gather its rows, C^(n)T on the matrix
-    // cores, D^(n) by prefix/suffix products; returns xhat (all four lanes of
-    // the column hold it).
-    __device__ __forceinline__ float forward(const int32_t *const *idx,
-                                             const float *const *A,
-                                             const uint16_t *const *A16,
-                                             int64_t ps, int *rows) {
-        RowFrag<KQ, BF> arow[N];
+    // Gather the rows of sample ps (this lane's column).
+    __device__ __forceinline__ void gather(const int32_t *const *idx,
+                                           const float *const *A,
+                                           const uint16_t *const *A16,
+                                           int64_t ps, int *rows,
+                                           RowFrag<KQ, BF> *arow) const {
 #pragma unroll
         for (int n = 0; n < N; ++n) {
             rows[n] = idx[n][ps];
             arow[n].load(A[n], A16[n], (int64_t)rows[n] * J4 + KQ * q);
         }
+    }
+
+    // C^(n)T on the matrix cores, D^(n) by prefix/suffix products; returns
+    // xhat of this lane's sample (all four lanes of the column hold it).
+    __device__ __forceinline__ float forward(const int32_t *const *idx,
+                                             const float *const *A,
+                                             const uint16_t *const *A16,
+                                             int64_t ps, int *rows) {
+        RowFrag<KQ, BF> arow[N];
+        gather(idx, A, A16, ps, rows, arow);
+        return contract_rows(arow);
+    }
+
+    __device__ __forceinline__ float contract_rows(
+        const RowFrag<KQ, BF> *arow) {
         floatx4 C[N][RB];
 #pragma unroll
         for (int n = 0; n < N; ++n)
@@ -126,22 +141,60 @@ struct FactorTile {
     }
 };
 
+// The block copies B^(1..N) into LDS once (float4 loads) and every wave
+// takes its two operand layouts from there.
+template <int N, int E>
+__device__ __forceinline__ void stage_B(const float *const *B, float *sB,
+                                        const float **sBm) {
+#pragma unroll
+    for (int n = 0; n < N; ++n) {
+        const float4 *src = reinterpret_cast<const float4 *>(B[n]);
+        float4 *dst = reinterpret_cast<float4 *>(sB + n * E);
+        for (int i = threadIdx.x; i < E / 4; i += kFactorThreads)
+            dst[i] = src[i];
+        sBm[n] = sB + n * E;
+    }
+    __syncthreads();
+}
+
+// Each wave sweeps kFactorTilesPerWave tiles and issues the next tile's
+// index and row loads before the current tile's arithmetic.
 template <int N, int KQ, int RB, bool BF>
 __global__ __launch_bounds__(kFactorThreads) void factor_grad_kernel(
     FactorArgs a, int ntiles) {
     using T = FactorTile<N, KQ, RB, BF>;
+    __shared__ float sB[N * T::J4 * T::R16];
+    const float *sBm[N];
+    stage_B<N, T::J4 * T::R16>(a.B, sB, sBm);
     T tl;
-    tl.load_B(a.B);
+    tl.load_B(sBm);
     double loss = 0.0;
     const int nwaves = gridDim.x * (kFactorThreads / 64);
-    for (int tile = blockIdx.x * (kFactorThreads / 64) + (threadIdx.x >> 6);
-         tile < ntiles; tile += nwaves) {
+    int tile = blockIdx.x * (kFactorThreads / 64) + (threadIdx.x >> 6);
+    int rows_n[N];
+    RowFrag<KQ, BF> arow_n[N];
+    float x_n = 0.f;
+    if (tile < ntiles) {
+        const int p = tile * 16 + tl.c;
+        const int ps = p < a.m ? p : a.m - 1;
+        tl.gather(a.idx, a.A, a.A16, ps, rows_n, arow_n);
+        x_n = a.val[ps];
+    }
+    for (; tile < ntiles; tile += nwaves) {
         const int p = tile * 16 + tl.c;
         const bool valid = p < a.m;
-        const int ps = valid ? p : a.m - 1;
-        int rows[N];
-        const float xh = tl.forward(a.idx, a.A, a.A16, ps, rows);
-        const float r = valid ? xh - a.val[ps] : 0.f;
+        RowFrag<KQ, BF> arow[N];
+#pragma unroll
+        for (int n = 0; n < N; ++n) arow[n] = arow_n[n];
+        const float x = x_n;
+        if (tile + nwaves < ntiles) {
+            const int pn = (tile + nwaves) * 16 + tl.c;
+            const int psn = pn < a.m ? pn : a.m - 1;
+            tl.gather(a.idx, a.A, a.A16, psn, rows_n, arow_n);
+            x_n = a.val[psn];
+        }
+        const float xh = tl.contract_rows(arow);
+        const float r = valid ? xh - x : 0.f;
         if (valid && tl.q == 0) loss += 0.5 * (double)r * (double)r;
 #pragma unroll
         for (int n = 0; n < N; ++n) {
@@ -167,8 +220,11 @@ __global__ __launch_bounds__(kFactorThreads) void factor_grad_kernel(
 template <int N, int KQ, int RB>
 __global__ __launch_bounds__(kFactorThreads) void hogwild_kernel(HogArgs a) {
     using T = FactorTile<N, KQ, RB, false>;
+    __shared__ float sB[N * T::J4 * T::R16];
+    const float *sBm[N];
+    stage_B<N, T::J4 * T::R16>(a.B, sB, sBm);
     T tl;
-    tl.load_B(a.B);
+    tl.load_B(sBm);
     const int64_t ntiles = (a.count + 15) / 16;
     const int64_t nwaves = (int64_t)gridDim.x * (kFactorThreads / 64);
     for (int64_t tile = (int64_t)blockIdx.x * (kFactorThreads / 64) +
@@ -344,50 +400,74 @@ __device__ __forceinline__ void finish_row(const SegArgs &a, int n,
 // 1..32; a lane adds the value d lanes below when that lane belongs to its
 // segment) leaves every row's sum in the lane of its last sample, which
 // finishes the row -- unless the row's samples cross a chunk edge.
-// Crossing part (the remaining blocks): one 256-thread block per crossing
-// row, from the builder's list; thread t sums samples t, t+256, ... and a
-// fixed LDS tree adds the 256 partial rows. No block depends on another and
+// Crossing part (the remaining blocks): one 1024-thread block per crossing
+// row, from the builder's list; thread t sums samples t, t+1024, ... (four
+// loads in flight), a fixed butterfly adds each wave's lanes and thread 0
+// adds the 16 wave sums in order. No block depends on another and
 // every addition order is fixed by the data, so results are reproducible.
+constexpr int kSegThreads = 1024;      // 16 waves: 16 chunks, or one row
+constexpr int kSegUnroll = 4;
+
 template <int KQ>
-__global__ __launch_bounds__(256) void seg_reduce_kernel(SegArgs a,
-                                                         int chunk_blocks) {
+__global__ __launch_bounds__(kSegThreads) void seg_reduce_kernel(
+    SegArgs a, int chunk_blocks) {
     constexpr int J4 = 4 * KQ;
-    __shared__ float red[256][J4 + 1];
+    __shared__ float red[kSegThreads / 64][J4 + 1];
     if ((int)blockIdx.x >= chunk_blocks) {
-        const int j = blockIdx.x - chunk_blocks;
-        const int n = j / a.xcap, e = j % a.xcap;
-        if (e >= a.xcount[n]) return;             // uniform per block
-        const int2 se = a.xlist[n][e];
-        const int t = threadIdx.x;
+        // crossing row j of this minibatch, listed mode after mode
+        int j = blockIdx.x - chunk_blocks, n = 0;
+        while (n < a.N && j >= a.xcount[n]) j -= a.xcount[n++];
+        if (n == a.N) return;                    // surplus block
+        const int2 se = a.xlist[n][j];
+        const int t = threadIdx.x, lane = t & 63, w = t >> 6;
         float acc[J4];
 #pragma unroll
         for (int q = 0; q < J4; ++q) acc[q] = 0.f;
         const float *G = a.G + (int64_t)n * a.m * J4;
-        for (int i = se.x + t; i < se.y; i += 256) {
-            float g[J4];
-            load_row_part<J4>(G + (int64_t)a.pos[n][i] * J4, g);
+        for (int i = se.x + t; i < se.y; i += kSegThreads * kSegUnroll) {
+            int ps[kSegUnroll];
 #pragma unroll
-            for (int q = 0; q < J4; ++q) acc[q] += g[q];
+            for (int u = 0; u < kSegUnroll; ++u) {
+                const int iu = i + u * kSegThreads;
+                ps[u] = iu < se.y ? (int)a.pos[n][iu] : -1;
+            }
+            float g[kSegUnroll][J4];
+#pragma unroll
+            for (int u = 0; u < kSegUnroll; ++u) {
+                if (ps[u] >= 0) {
+                    load_row_part<J4>(G + (int64_t)ps[u] * J4, g[u]);
+                } else {
+#pragma unroll
+                    for (int q = 0; q < J4; ++q) g[u][q] = 0.f;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kSegUnroll; ++u)
+#pragma unroll
+                for (int q = 0; q < J4; ++q) acc[q] += g[u][q];
         }
 #pragma unroll
-        for (int q = 0; q < J4; ++q) red[t][q] = acc[q];
+        for (int d = 32; d >= 1; d >>= 1)
+#pragma unroll
+            for (int q = 0; q < J4; ++q) acc[q] += __shfl_xor(acc[q], d);
+        if (lane == 0)
+#pragma unroll
+            for (int q = 0; q < J4; ++q) red[w][q] = acc[q];
         __syncthreads();
-        for (int stride = 128; stride >= 1; stride >>= 1) {
-            if (t < stride)
-#pragma unroll
-                for (int q = 0; q < J4; ++q) red[t][q] += red[t + stride][q];
-            __syncthreads();
-        }
         if (t == 0) {
             float g[J4];
 #pragma unroll
-            for (int q = 0; q < J4; ++q) g[q] = red[0][q];
+            for (int q = 0; q < J4; ++q) {
+                float v = 0.f;
+                for (int ww = 0; ww < kSegThreads / 64; ++ww) v += red[ww][q];
+                g[q] = v;
+            }
             finish_row<J4>(a, n, a.rows[n][se.x], g, se.y - se.x, se.x);
         }
         return;
     }
     const int lane = threadIdx.x & 63;
-    const int gw = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int gw = blockIdx.x * (kSegThreads / 64) + (threadIdx.x >> 6);
     if (gw >= a.N * a.nchunks) return;           // uniform per wave
     const int n = gw / a.nchunks, c = gw % a.nchunks;
     const int i0 = c * kSegChunk, i = i0 + lane;
@@ -431,9 +511,10 @@ __global__ __launch_bounds__(256) void seg_reduce_kernel(SegArgs a,
 
 template <int KQ>
 static hipError_t launch_seg_kq(const SegArgs &a, hipStream_t s) {
-    const int chunk_blocks = (a.N * a.nchunks + 3) / 4;
-    const int blocks = chunk_blocks + a.N * a.xcap;
-    FT_LAUNCH(seg_reduce_kernel<KQ>, dim3(blocks), dim3(256), 0, s, a,
+    const int chunk_blocks =
+        (a.N * a.nchunks + kSegThreads / 64 - 1) / (kSegThreads / 64);
+    const int blocks = chunk_blocks + a.ncross;
+    FT_LAUNCH(seg_reduce_kernel<KQ>, dim3(blocks), dim3(kSegThreads), 0, s, a,
               chunk_blocks);
     return hipGetLastError();
 }

@@ -1,9 +1,12 @@
 """Integer-only references for the builder (no floating point, no oracle).
 
 feistel_order: the counter-based epoch order from its definition -- a
-4-round balanced Feistel network on 2h bits with the SplitMix64 finaliser as
-round function (Steele, Lea & Flood 2014), round keys the SplitMix64 stream
-from the key, restricted to [0, n) by cycle walking (Black & Rogaway 2002).
+4-round Feistel network on the mixed-radix domain Z_a x Z_b, a = ceil(sqrt n),
+b = ceil(n / a) (Black & Rogaway 2002): x = L b + R, a round maps
+(L in Z_p, R in Z_q) to (R, (L + F(R)) mod p) and swaps the moduli; F is the
+MurmurHash3 32-bit finaliser of R ^ k scaled into [0, p) by (h p) >> 32; round
+keys are the high halves of the SplitMix64 stream from the key (Steele, Lea &
+Flood 2014); values >= n are cycle-walked.
 
 minibatch_sort: per minibatch and mode, the positions sorted stably by row.
 """
@@ -26,6 +29,15 @@ def epoch_key(shuffle_seed, epoch, salt=0):
             GOLDEN * np.uint64(2 * epoch + 1 + 2 * salt))
 
 
+def _fmix32(h):
+    m = np.uint64(0xFFFFFFFF)
+    h = h ^ (h >> np.uint64(16))
+    h = (h * np.uint64(0x85EBCA6B)) & m
+    h = h ^ (h >> np.uint64(13))
+    h = (h * np.uint64(0xC2B2AE35)) & m
+    return h ^ (h >> np.uint64(16))
+
+
 def feistel_order(n, key):
     key = np.uint64(key)
     with np.errstate(over="ignore"):
@@ -33,27 +45,28 @@ def feistel_order(n, key):
         st = key
         for _ in range(4):
             st = st + GOLDEN
-            ks.append(_mix64(np.array([st], dtype=np.uint64))[0])
-        bits = 2
-        while (1 << bits) < n:
-            bits += 1
-        if bits & 1:
-            bits += 1
-        h = np.uint64(bits // 2)
-        mask = np.uint64((1 << (bits // 2)) - 1)
+            ks.append(_mix64(np.array([st], dtype=np.uint64))[0]
+                      >> np.uint64(32))
+    a = 1
+    while a * a < n:
+        a += 1
+    b = -(-n // a)
+    A, B = np.uint64(a), np.uint64(b)
 
-        def enc(x):
-            L = x >> h
-            R = x & mask
-            for k in ks:
-                L, R = R, L ^ (_mix64(R ^ k) & mask)
-            return (L << h) | R
+    def enc(x):
+        L, R = x // B, x % B
+        p, q = A, B
+        for k in ks:
+            f = (_fmix32(R ^ k) * p) >> np.uint64(32)
+            L, R = R, (L + f) % p
+            p, q = q, p
+        return L * B + R
 
-        x = enc(np.arange(n, dtype=np.uint64))
+    x = enc(np.arange(n, dtype=np.uint64))
+    bad = x >= np.uint64(n)
+    while bad.any():
+        x[bad] = enc(x[bad])
         bad = x >= np.uint64(n)
-        while bad.any():
-            x[bad] = enc(x[bad])
-            bad = x >= np.uint64(n)
     return x.astype(np.int64)
 
 

@@ -60,6 +60,7 @@ struct ft_handle {
     float *pval = nullptr;
     uint32_t *sk[2][kMaxOrder] = {};
     uint32_t *sv[2][kMaxOrder] = {};
+    uint32_t *inv[kMaxOrder] = {};     // sorted index of every position
     uint32_t *counts = nullptr;
     size_t counts_cap = 0;
     int sort_final = 0;
@@ -69,7 +70,7 @@ struct ft_handle {
     // factor-phase scratch
     float *G = nullptr;
     size_t G_cap = 0;
-    int2 *xlist = nullptr;            // crossing rows per minibatch and mode
+    int4 *xlist = nullptr;            // crossing rows per minibatch and mode
     size_t xlist_cap = 0;
     int32_t *xcount = nullptr;
     size_t xcount_cap = 0;
@@ -253,6 +254,7 @@ static void release(ft_handle *h) {
             dfree(h->sk[s][n]);
             dfree(h->sv[s][n]);
         }
+        dfree(h->inv[n]);
         dfree(h->pidx[n]);
     }
     dfree(h->val[0]);
@@ -544,6 +546,9 @@ extern "C" ft_status ft_set_nonzeros(ft_handle *h, ft_set which, int64_t nnz,
             dfree(h->pidx[n]);
             h->pidx[n] = nullptr;
             HIPCHK(h, hipMalloc(&h->pidx[n], sizeof(int32_t) * nnz));
+            dfree(h->inv[n]);
+            h->inv[n] = nullptr;
+            HIPCHK(h, hipMalloc(&h->inv[n], sizeof(uint32_t) * nnz));
             for (int s = 0; s < 2; ++s) {
                 dfree(h->sk[s][n]);
                 dfree(h->sv[s][n]);
@@ -644,6 +649,7 @@ static ft_status build_minibatches(ft_handle *h) {
             p.val_in[n] = pass == 0 ? nullptr : h->sv[cur][n];
             p.key_out[n] = h->sk[pass == 0 ? 0 : cur ^ 1][n];
             p.val_out[n] = h->sv[pass == 0 ? 0 : cur ^ 1][n];
+            p.inv_out[n] = pass == passes - 1 ? h->inv[n] : nullptr;
         }
         cur = pass == 0 ? 0 : cur ^ 1;
         HIPCHK(h, launch_sort_pass(p, h->stream));
@@ -657,16 +663,16 @@ static ft_status build_minibatches(ft_handle *h) {
     cx.xcap = cross_capacity(std::min<int64_t>(M, nnz));
     for (int n = 0; n < h->N; ++n) cx.rows[n] = h->sk[cur][n];
     HIPCHK(h, ensure(&h->xlist, &h->xlist_cap, (size_t)nseg * h->N * cx.xcap));
-    HIPCHK(h, ensure(&h->xcount, &h->xcount_cap, (size_t)nseg * h->N));
+    HIPCHK(h, ensure(&h->xcount, &h->xcount_cap, (size_t)nseg * h->N * 2));
     cx.xlist = h->xlist;
     cx.xcount = h->xcount;
     h->xcap = cx.xcap;
     HIPCHK(h, launch_crossing_segments(cx, h->stream));
     // the crossing-row counts size the reduction grids: one read-back per
     // epoch instead of a worst-case grid per minibatch
-    h->xcount_host.resize((size_t)nseg * h->N);
+    h->xcount_host.resize((size_t)nseg * h->N * 2);
     HIPCHK(h, hipMemcpyAsync(h->xcount_host.data(), h->xcount,
-                             sizeof(int32_t) * nseg * h->N,
+                             sizeof(int32_t) * nseg * h->N * 2,
                              hipMemcpyDeviceToHost, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
     return FT_OK;
@@ -705,6 +711,7 @@ static ft_status run_minibatch(ft_handle *h, int64_t b, int apply,
     fa.val = h->pval + off;
     fa.m = m;
     fa.G = h->G;
+    for (int n = 0; n < h->N; ++n) fa.inv[n] = h->inv[n] + off;
     fa.loss_part = loss_part;
     int nb = 0;
     {
@@ -718,7 +725,6 @@ static ft_status run_minibatch(ft_handle *h, int64_t b, int apply,
     sa.nchunks = (m + kSegChunk - 1) / kSegChunk;
     for (int n = 0; n < h->N; ++n) {
         sa.rows[n] = h->sk[h->sort_final][n] + off;
-        sa.pos[n] = h->sv[h->sort_final][n] + off;
         sa.A[n] = h->A[n];
         sa.A16[n] = h->sh.bf16 ? h->A16[n] : nullptr;
         sa.xlist[n] = h->xlist + ((size_t)b * h->N + n) * h->xcap;
@@ -726,10 +732,16 @@ static ft_status run_minibatch(ft_handle *h, int64_t b, int apply,
         sa.count[n] = count ? count[n] : nullptr;
     }
     sa.G = h->G;
-    sa.xcount = h->xcount + (size_t)b * h->N;
+    sa.xcount = h->xcount + (size_t)b * h->N * 2;
     sa.xcap = h->xcap;
-    sa.ncross = 0;
-    for (int n = 0; n < h->N; ++n) sa.ncross += h->xcount_host[b * h->N + n];
+    sa.host_counts = 1;
+    sa.xs[0] = sa.xl[0] = 0;
+    for (int n = 0; n < h->N; ++n) {
+        sa.xs[n + 1] = sa.xs[n] + h->xcount_host[(b * h->N + n) * 2];
+        sa.xl[n + 1] = sa.xl[n] + h->xcount_host[(b * h->N + n) * 2 + 1];
+    }
+    sa.small_blocks = (sa.xs[h->N] + kSegWaves - 1) / kSegWaves;
+    sa.large_blocks = sa.xl[h->N];
     sa.lr = (float)h->opt.lr_A;
     sa.lam = (float)h->opt.lambda_A;
     sa.mean = h->opt.row_scale == FT_ROW_MEAN;
@@ -1178,7 +1190,7 @@ extern "C" ft_status ft_profile_get(ft_handle *h, int32_t kernel,
 // ------------------------------------------------------------------ stateless
 namespace {
 struct MbLayout {
-    size_t bpad, G, sk0, sk1, sv0, sv1, counts, xlist, xcount, ordinal,
+    size_t bpad, G, sk0, sk1, sv0, sv1, inv, counts, xlist, xcount, ordinal,
         tile_count, total, core_part, dpart, bytes;
     int xcap;
     int tps, nch, ntiles_scan, nb_core, nb_fact, nb_eval;
@@ -1232,10 +1244,11 @@ MbLayout mb_layout(const ft_problem_desc *p, int64_t m) {
     L.sk1 = take(sizeof(uint32_t) * N * m);
     L.sv0 = take(sizeof(uint32_t) * N * m);
     L.sv1 = take(sizeof(uint32_t) * N * m);
+    L.inv = take(sizeof(uint32_t) * N * m);
     L.counts = take(sizeof(uint32_t) * N * kRadix * L.tps);
     L.xcap = cross_capacity(m);
-    L.xlist = take(sizeof(int2) * N * L.xcap);
-    L.xcount = take(sizeof(int32_t) * N);
+    L.xlist = take(sizeof(int4) * N * L.xcap);
+    L.xcount = take(sizeof(int32_t) * N * 2);
     L.ordinal = take(sizeof(uint32_t) * N * m);
     L.tile_count = take(sizeof(uint32_t) * N * L.ntiles_scan);
     L.total = take(sizeof(int64_t) * N);
@@ -1366,10 +1379,11 @@ extern "C" ft_status ft_mb_backward(
     fa.m = (int32_t)m;
     fa.G = at<float>(workspace, L.G);
     fa.loss_part = at<double>(workspace, L.dpart);
-    int nb = 0;
-    HIPCHK0(launch_factor_grad(L.sh, fa, &nb, s));
+    uint32_t *inv = at<uint32_t>(workspace, L.inv);
+    for (int n = 0; n < N; ++n) fa.inv[n] = inv + (size_t)n * m;
 
-    // sort the minibatch's rows per mode (one segment)
+    // sort the minibatch's rows per mode (one segment); the last pass also
+    // gives the sorted slot of every sample, where its gradients go
     SortPass sp{};
     sp.N = N;
     sp.nnz = m;
@@ -1396,10 +1410,13 @@ extern "C" ft_status ft_mb_backward(
             sp.val_in[n] = pass == 0 ? nullptr : sv[cur] + (size_t)n * m;
             sp.key_out[n] = sk[out] + (size_t)n * m;
             sp.val_out[n] = sv[out] + (size_t)n * m;
+            sp.inv_out[n] = pass == passes - 1 ? inv + (size_t)n * m : nullptr;
         }
         HIPCHK0(launch_sort_pass(sp, s));
         cur = out;
     }
+    int nb = 0;
+    HIPCHK0(launch_factor_grad(L.sh, fa, &nb, s));
 
     SegArgs sa{};
     sa.N = N;
@@ -1417,17 +1434,19 @@ extern "C" ft_status ft_mb_backward(
         cx.nseg = 1;
         cx.xcap = L.xcap;
         for (int n = 0; n < N; ++n) cx.rows[n] = sk[cur] + (size_t)n * m;
-        cx.xlist = at<int2>(workspace, L.xlist);
+        cx.xlist = at<int4>(workspace, L.xlist);
         cx.xcount = at<int32_t>(workspace, L.xcount);
         HIPCHK0(launch_crossing_segments(cx, s));
         sa.xcount = cx.xcount;
         sa.xcap = L.xcap;
-        sa.ncross = N * L.xcap;        // worst case; surplus blocks exit
+        // worst case (surplus blocks exit): every crossing row short, and
+        // as many long rows as fit in m
+        sa.small_blocks = (N * L.xcap + kSegWaves - 1) / kSegWaves;
+        sa.large_blocks = N * (int)(m / (kSmallCross + 1));
         for (int n = 0; n < N; ++n) sa.xlist[n] = cx.xlist + (size_t)n * L.xcap;
     }
     for (int n = 0; n < N; ++n) {
         sa.rows[n] = sk[cur] + (size_t)n * m;
-        sa.pos[n] = sv[cur] + (size_t)n * m;
         sa.A[n] = const_cast<float *>(A[n]);
         sa.grad[n] = gradA ? gradA[n] : nullptr;
         if (gradA)

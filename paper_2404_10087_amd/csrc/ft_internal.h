@@ -35,6 +35,9 @@ constexpr int kMaxR = 32;
 // Sorted segmented reduction: rows are summed over fixed chunks of this many
 // sorted samples; segments that cross a chunk edge are finished by a fix-up.
 constexpr int kSegChunk = 64;
+constexpr int kSmallCross = 256;      // crossing rows up to this many samples
+                                      // are reduced by one wave
+constexpr int kSegWaves = 16;         // waves per row-reduction block
 
 // Mode-sorted minibatch builder: LSD radix sort, 8-bit digits, 2048-element
 // tiles aligned to minibatch starts.
@@ -81,6 +84,8 @@ struct SortPass {
     const uint32_t *val_in[kMaxOrder];   // nullptr: payload = position in segment
     uint32_t *key_out[kMaxOrder];
     uint32_t *val_out[kMaxOrder];
+    uint32_t *inv_out[kMaxOrder];   // final pass only (else nullptr):
+                                    // inv[seg + pos] = sorted index in seg
     uint32_t *counts;    // [N][nseg][tiles_per_seg][kRadix]
 };
 hipError_t launch_sort_pass(const SortPass &p, hipStream_t s);
@@ -93,7 +98,10 @@ struct FactorArgs {
     int32_t m;
     const float *A[kMaxOrder];
     const float *B[kMaxOrder];
-    float *G;                        // [N][m][J4] per-sample row gradients
+    // per-sample row gradients, [N][m][J4] in each mode's sorted order:
+    // sample p of mode n goes to row inv[n][p]
+    float *G;
+    const uint32_t *inv[kMaxOrder];
     double *loss_part;               // one per block
 };
 hipError_t launch_factor_grad(const Shape &sh, const FactorArgs &a, int *nblocks,
@@ -118,15 +126,22 @@ struct SegArgs {
     int32_t m;
     int nchunks;                      // ceil(m / kSegChunk)
     const uint32_t *rows[kMaxOrder];  // sorted rows of the minibatch
-    const uint32_t *pos[kMaxOrder];   // sorted in-minibatch positions
-    const float *G;                   // [N][m][J4]
+    const float *G;                   // [N][m][J4], sorted order per mode
     float *A[kMaxOrder];
-    // rows whose samples cross a chunk edge: (first, end) sorted indices,
-    // xcount[n] of them for mode n (capacity xcap each)
-    const int2 *xlist[kMaxOrder];
+    // rows whose samples cross a chunk edge, entries (first, end, row, -)
+    // in sorted indices. For mode n, xcount[2n] rows of at most kSmallCross
+    // samples fill xlist[n][0..) and xcount[2n+1] longer rows fill
+    // xlist[n][xcap-1..] downwards.
+    const int4 *xlist[kMaxOrder];
     const int32_t *xcount;
     int xcap;
-    int ncross;                       // sum of xcount over the modes (host)
+    // host_counts: the counts are also given here as prefix sums over the
+    // modes (xs: short rows, xl: long rows), so blocks find their entry
+    // without reading xcount
+    int host_counts;
+    int xs[kMaxOrder + 1], xl[kMaxOrder + 1];
+    int small_blocks;                 // blocks for the short rows (16 each)
+    int large_blocks;                 // blocks for the long rows (one each)
     float lr, lam;
     int mean;                         // FT_ROW_MEAN
     int apply;                        // 1: update A; 0: write grad/count;
@@ -153,8 +168,8 @@ struct CrossArgs {
     int nseg;
     int xcap;                         // max(1, ceil(min(M, nnz) / kSegChunk) - 1)
     const uint32_t *rows[kMaxOrder];  // sorted rows of the whole epoch
-    int2 *xlist;                      // [nseg][N][xcap]
-    int32_t *xcount;                  // [nseg][N], zeroed by the launcher
+    int4 *xlist;                      // [nseg][N][xcap]
+    int32_t *xcount;                  // [nseg][N][2] (short, long rows)
 };
 hipError_t launch_crossing_segments(const CrossArgs &c, hipStream_t s);
 inline int cross_capacity(int64_t m) {

@@ -234,6 +234,31 @@ __device__ __forceinline__ TileInfo tile_info(const SortPass &p, int b,
     return t;
 }
 
+// XCD-aware tile mapping: workgroups are dealt to the 8 XCDs round-robin by
+// their linear id, so linear id L runs on XCD L % 8. All tiles of one
+// (mode, minibatch) segment are given ids with the same residue, so a
+// segment's scattered output (digit runs, and in the final pass the inverse
+// positions) is assembled in one L2 before it is written back. Returns false
+// for the surplus ids of the last group.
+constexpr int kXcds = 8;
+
+__device__ __forceinline__ bool sort_tile_of(const SortPass &p, int &tb,
+                                             int &b, int &n) {
+    const int L = blockIdx.x;
+    const int slot = L / kXcds;
+    const int sn = (slot / p.tiles_per_seg) * kXcds + L % kXcds;
+    if (sn >= p.nseg * p.N) return false;
+    tb = slot % p.tiles_per_seg;
+    n = sn / p.nseg;
+    b = sn % p.nseg;
+    return true;
+}
+
+static int sort_grid(const SortPass &p) {
+    const int groups = (p.nseg * p.N + kXcds - 1) / kXcds;
+    return groups * kXcds * p.tiles_per_seg;
+}
+
 // counts of tile tb of segment b, mode n: kRadix consecutive words
 __device__ __forceinline__ uint32_t *counts_at(const SortPass &p, int n, int b,
                                                int tb) {
@@ -241,10 +266,11 @@ __device__ __forceinline__ uint32_t *counts_at(const SortPass &p, int n, int b,
                           kRadix;
 }
 
-// grid: (tiles_per_seg, nseg, N). Digit histogram of one tile; every wave
+// One block per tile (sort_tile_of). Digit histogram of one tile; every wave
 // counts into its own LDS histogram so hot rows contend only within a wave.
 __global__ __launch_bounds__(kSortThreads) void sort_upsweep_kernel(SortPass p) {
-    const int tb = blockIdx.x, b = blockIdx.y, n = blockIdx.z;
+    int tb, b, n;
+    if (!sort_tile_of(p, tb, b, n)) return;
     TileInfo t = tile_info(p, b, tb);
     if (t.tile_len == 0) return;
     constexpr int W = kSortThreads / 64;
@@ -269,7 +295,7 @@ __global__ __launch_bounds__(kSortThreads) void sort_upsweep_kernel(SortPass p) 
     counts_at(p, n, b, tb)[threadIdx.x] = c;
 }
 
-// grid: (tiles_per_seg, nseg, N). Stable scatter, staged in LDS. The global
+// One block per tile (sort_tile_of). Stable scatter, staged in LDS. The global
 // start of digit d for this tile is the exclusive scan over digits of the
 // segment's digit totals plus the counts of d in the tiles before this one
 // (read from the upsweep's histograms). The tile is then ordered by digit
@@ -277,10 +303,13 @@ __global__ __launch_bounds__(kSortThreads) void sort_upsweep_kernel(SortPass p) 
 // is the number of equal digits before it in the tile, taken round by round
 // -- 256 consecutive elements per round -- from wave match masks and per-wave
 // counts), then written out so that consecutive threads store consecutive
-// positions of one digit's run.
+// positions of one digit's run. The final pass also records, for every
+// in-minibatch position, its sorted index (the factor kernel writes each
+// sample's gradient rows straight to their sorted slots).
 __global__ __launch_bounds__(kSortThreads) void sort_downsweep_kernel(
     SortPass p) {
-    const int tb = blockIdx.x, b = blockIdx.y, n = blockIdx.z;
+    int tb, b, n;
+    if (!sort_tile_of(p, tb, b, n)) return;
     TileInfo t = tile_info(p, b, tb);
     if (t.tile_len == 0) return;
     __shared__ uint32_t base[kRadix];     // global start of digit d (this tile)
@@ -382,73 +411,109 @@ __global__ __launch_bounds__(kSortThreads) void sort_downsweep_kernel(
         run[tid] += add;
         __syncthreads();
     }
+    uint32_t *inv = p.inv_out[n] ? p.inv_out[n] + t.seg_start : nullptr;
     for (int k = tid; k < t.tile_len; k += kSortThreads) {
         const uint32_t kk = skey[k];
         const uint32_t d = (kk >> p.shift) & (kRadix - 1);
         const uint32_t dst = base[d] + (uint32_t)k - lstart[d];
         kout[dst] = kk;
         vout[dst] = sval[k];
+        if (inv) inv[sval[k]] = dst;
     }
 }
 
 // ------------------------------------------------------------------ crossings
-// One thread per chunk edge q = k * kSegChunk (k >= 1) of every minibatch and
-// mode: if the row at q also occupies q - 1 and its first sample lies in the
-// chunk just before q (so q is the first edge the row crosses), record the
-// row's (first, end) sorted indices. The first sample is found in that
-// 64-entry chunk, the end by a galloping search. The list order is
-// arbitrary; every entry is reduced independently.
-__global__ void crossing_segments_kernel(CrossArgs c) {
-    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t per_seg = (int64_t)c.N * c.xcap;
-    if (tid >= (int64_t)c.nseg * per_seg) return;
-    const int b = (int)(tid / per_seg);
-    const int n = (int)((tid % per_seg) / c.xcap);
-    const int k = (int)(tid % c.xcap) + 1;
+// One block per minibatch and mode, one thread per chunk edge q = k kSegChunk
+// (k = 1 .. xcap, in rounds of kCrossThreads edges). A thread whose edge is
+// the first one its row crosses (the row occupies q - 1 and q but not
+// q - kSegChunk - 1) finds the row's first sample in the chunk before q and
+// its end by a galloping search, and lists (first, end, row). Rows of at most kSmallCross samples are
+// listed from the front of the minibatch's list, longer ones from the back,
+// each class in edge order: slots come from a block scan of the flags (wave
+// ballots, then wave totals in LDS), so no atomics and the list is the same
+// on every run.
+constexpr int kCrossThreads = 1024;
+
+__global__ __launch_bounds__(kCrossThreads) void crossing_segments_kernel(
+    CrossArgs c) {
+    const int b = blockIdx.x, n = blockIdx.y;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    constexpr int W = kCrossThreads / 64;
+    __shared__ int wtot[2][W];
     const int64_t off = (int64_t)b * c.M;
     const int64_t rem = c.nnz - off;
     const int m = (int)(rem < c.M ? rem : c.M);
-    const int q = k * kSegChunk;
-    if (q >= m) return;
     const uint32_t *r = c.rows[n] + off;
-    const uint32_t row = r[q];
-    if (r[q - 1] != row) return;
-    if (q > kSegChunk && r[q - kSegChunk - 1] == row) return;  // crossed earlier
-    int lo = q - kSegChunk, hi = q;               // first index of row
-    while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (r[mid] < row) lo = mid + 1; else hi = mid;
+    int4 *list = c.xlist + ((int64_t)b * c.N + n) * c.xcap;
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    int nsmall = 0, nlarge = 0;
+    for (int k0 = 1; k0 <= c.xcap; k0 += kCrossThreads) {
+        const int k = k0 + t;
+        const int q = k * kSegChunk;
+        bool flag = false;
+        int first = 0, end = 0;
+        uint32_t row = 0;
+        if (k <= c.xcap && q < m) {
+            row = r[q];
+            flag = r[q - 1] == row &&
+                   !(q > kSegChunk && r[q - kSegChunk - 1] == row);
+            if (flag) {
+                int lo = q - kSegChunk, hi = q;
+                while (lo < hi) {
+                    const int mid = (lo + hi) >> 1;
+                    if (r[mid] < row) lo = mid + 1; else hi = mid;
+                }
+                first = lo;
+                int step = kSegChunk, probe = q;
+                while (probe + step < m && r[probe + step] == row) {
+                    probe += step;
+                    step <<= 1;
+                }
+                lo = probe + 1;
+                hi = probe + step < m ? probe + step : m;
+                while (lo < hi) {
+                    const int mid = (lo + hi) >> 1;
+                    if (r[mid] == row) lo = mid + 1; else hi = mid;
+                }
+                end = lo;
+            }
+        }
+        const bool small = flag && end - first <= kSmallCross;
+        const bool large = flag && !small;
+        const uint64_t bs = __ballot(small), bl = __ballot(large);
+        if (lane == 0) {
+            wtot[0][w] = __popcll(bs);
+            wtot[1][w] = __popcll(bl);
+        }
+        __syncthreads();
+        int ps = nsmall, pl = nlarge;
+        for (int v = 0; v < w; ++v) {
+            ps += wtot[0][v];
+            pl += wtot[1][v];
+        }
+        const int4 e = make_int4(first, end, (int)row, 0);
+        if (small) list[ps + __popcll(bs & lt)] = e;
+        if (large) list[c.xcap - 1 - (pl + __popcll(bl & lt))] = e;
+        for (int v = 0; v < W; ++v) {
+            nsmall += wtot[0][v];
+            nlarge += wtot[1][v];
+        }
+        __syncthreads();
     }
-    const int first = lo;
-    int step = kSegChunk, probe = q;              // end: gallop, then bisect
-    while (probe + step < m && r[probe + step] == row) {
-        probe += step;
-        step <<= 1;
+    if (t == 0) {
+        c.xcount[(b * c.N + n) * 2] = nsmall;
+        c.xcount[(b * c.N + n) * 2 + 1] = nlarge;
     }
-    lo = probe + 1;
-    hi = probe + step < m ? probe + step : m;
-    while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (r[mid] == row) lo = mid + 1; else hi = mid;
-    }
-    const int slot = atomicAdd(&c.xcount[b * c.N + n], 1);
-    c.xlist[((int64_t)b * c.N + n) * c.xcap + slot] = make_int2(first, lo);
 }
 
 hipError_t launch_crossing_segments(const CrossArgs &c, hipStream_t s) {
-    const int64_t counts = (int64_t)c.nseg * c.N;
-    hipError_t e = launch_fill_zero(reinterpret_cast<float *>(c.xcount),
-                                    counts, s);
-    if (e != hipSuccess) return e;
-    const int64_t threads = counts * c.xcap;
-    hipLaunchKernelGGL(crossing_segments_kernel,
-                       dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s,
-                       c);
+    hipLaunchKernelGGL(crossing_segments_kernel, dim3(c.nseg, c.N),
+                       dim3(kCrossThreads), 0, s, c);
     return hipGetLastError();
 }
 
 hipError_t launch_sort_pass(const SortPass &p, hipStream_t s) {
-    dim3 g3(p.tiles_per_seg, p.nseg, p.N);
+    dim3 g3(sort_grid(p));
     hipLaunchKernelGGL(sort_upsweep_kernel, g3, dim3(kSortThreads), 0, s, p);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

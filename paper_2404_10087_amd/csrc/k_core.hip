@@ -11,8 +11,8 @@
 // all of its tiles (the register accumulation of Algorithm 5); a block sums its
 // four waves in a fixed order and writes one partial per block.
 //
-// core_update_kernel: sums the block partials in a fixed order (no atomics)
-// and applies B^(n) <- B^(n) - lr_B (Grad^(n) / count + lambda_B B^(n)).
+// core_update_kernel: sums the block partials in a fixed order (no atomics:
+// 32 strided slices, then the slices in order) and applies B^(n) <- B^(n) - lr_B (Grad^(n) / count + lambda_B B^(n)).
 #include "ft_internal.h"
 #include "mfma_tile.h"
 
@@ -278,20 +278,34 @@ hipError_t launch_core_grad(const Shape &sh, const CoreArgs &a, int nblocks,
 
 // 64 consecutive elements per block; four slices of the partials each summed
 // in increasing block order, then the slices in order.
-__global__ __launch_bounds__(256) void core_update_kernel(CoreUpdateArgs a,
-                                                          int E, int J4,
-                                                          int R16) {
-    __shared__ float part[4][64];
-    const int el = threadIdx.x & 63, sl = threadIdx.x >> 6;
-    const int e = blockIdx.x * 64 + el;
+// One block per 32 consecutive elements of [N][J4][R16]; thread (slice sl,
+// element el) sums partials sl, sl + 32, ... (eight loads in flight), and
+// thread sl = 0 adds the 32 slice sums in order.
+constexpr int kUpdElems = 32, kUpdSlices = 32;
+
+__global__ __launch_bounds__(kUpdElems * kUpdSlices) void core_update_kernel(
+    CoreUpdateArgs a, int E, int J4, int R16) {
+    __shared__ float part[kUpdSlices][kUpdElems + 1];
+    const int el = threadIdx.x % kUpdElems, sl = threadIdx.x / kUpdElems;
+    const int e = blockIdx.x * kUpdElems + el;
     float acc = 0.f;
-    if (e < E)
-        for (int b = sl; b < a.nblocks; b += 4)
-            acc += a.part[(int64_t)b * E + e];
+    if (e < E) {
+        int b = sl;
+        for (; b + 7 * kUpdSlices < a.nblocks; b += 8 * kUpdSlices) {
+            float v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                v[u] = a.part[(int64_t)(b + u * kUpdSlices) * E + e];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) acc += v[u];
+        }
+        for (; b < a.nblocks; b += kUpdSlices) acc += a.part[(int64_t)b * E + e];
+    }
     part[sl][el] = acc;
     __syncthreads();
     if (sl == 0 && e < E) {
-        const float g = ((part[0][el] + part[1][el]) + part[2][el]) + part[3][el];
+        float g = 0.f;
+        for (int k = 0; k < kUpdSlices; ++k) g += part[k][el];
         if (a.grad_out) a.grad_out[e] = g;
         const int n = e / (J4 * R16);
         const int j = (e / R16) % J4, r = e % R16;
@@ -308,8 +322,8 @@ __global__ __launch_bounds__(256) void core_update_kernel(CoreUpdateArgs a,
 hipError_t launch_core_update(const Shape &sh, const CoreUpdateArgs &a,
                               hipStream_t s) {
     const int E = sh.N * sh.J4 * sh.R16;
-    FT_LAUNCH(core_update_kernel, dim3((E + 63) / 64), dim3(256), 0, s,
-                       a, E, sh.J4, sh.R16);
+    FT_LAUNCH(core_update_kernel, dim3((E + kUpdElems - 1) / kUpdElems),
+              dim3(kUpdElems * kUpdSlices), 0, s, a, E, sh.J4, sh.R16);
     return hipGetLastError();
 }
 

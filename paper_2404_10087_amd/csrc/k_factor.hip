@@ -10,7 +10,9 @@
 //     g^(n)_s = r_s * B^(n) d^(n)_s            (Eq. (8)),
 // again on the matrix cores as G^T = B^(n) (r (*) D^(n))^T, which lands in the
 // natural "sample-column" layout so it is stored as float4 rows with no
-// transpose. All reads use A and B as they stand at the minibatch start.
+// transpose, at the sample's slot in the mode's sorted order (from the
+// builder), so the row reduction reads each row's gradients contiguously.
+// All reads use A and B as they stand at the minibatch start.
 //
 // seg_reduce_kernel: the deterministic row reduction. The builder has sorted
 // every minibatch's samples by row (ties in minibatch order) and listed the
@@ -183,6 +185,9 @@ __global__ __launch_bounds__(kFactorThreads) void factor_grad_kernel(
     for (; tile < ntiles; tile += nwaves) {
         const int p = tile * 16 + tl.c;
         const bool valid = p < a.m;
+        uint32_t inv[N];
+#pragma unroll
+        for (int n = 0; n < N; ++n) inv[n] = valid ? a.inv[n][p] : 0u;
         RowFrag<KQ, BF> arow[N];
 #pragma unroll
         for (int n = 0; n < N; ++n) arow[n] = arow_n[n];
@@ -198,7 +203,7 @@ __global__ __launch_bounds__(kFactorThreads) void factor_grad_kernel(
         if (valid && tl.q == 0) loss += 0.5 * (double)r * (double)r;
 #pragma unroll
         for (int n = 0; n < N; ++n) {
-            float *Gn = a.G + ((int64_t)n * a.m + p) * T::J4;
+            float *Gn = a.G + ((int64_t)n * a.m + inv[n]) * T::J4;
 #pragma unroll
             for (int jb = 0; jb < T::JB; ++jb) {
                 const floatx4 g = tl.grad(n, jb, r);
@@ -354,11 +359,13 @@ hipError_t launch_hogwild(const Shape &sh, const HogArgs &a, hipStream_t s) {
 // ------------------------------------------------------------ row reduction
 // Finish one row of mode n whose summed per-sample gradient g[0..J4) over
 // cnt occurrences is complete; start is the sorted index of its first
-// occurrence. Writes the whole row (one lane).
+// occurrence and av the row's current value (unused for autograd output).
+// Writes the whole row (one lane).
 template <int J4>
-__device__ __forceinline__ void finish_row(const SegArgs &a, int n,
-                                           uint32_t row, const float (&g)[J4],
-                                           int cnt, int start) {
+__device__ __forceinline__ void finish_row_av(const SegArgs &a, int n,
+                                              uint32_t row, const float (&g)[J4],
+                                              int cnt, int start,
+                                              const float (&av)[J4]) {
     const int64_t off = (int64_t)row * J4;
     if (a.apply == 2) {
         // autograd: gradient of the data term only, times grad_out
@@ -374,8 +381,6 @@ __device__ __forceinline__ void finish_row(const SegArgs &a, int n,
         }
         return;
     }
-    float av[J4];
-    load_row_part<J4>(a.A[n] + off, av);
     float o[J4];
 #pragma unroll
     for (int j = 0; j < J4; ++j) o[j] = g[j] + (float)cnt * a.lam * av[j];
@@ -394,80 +399,142 @@ __device__ __forceinline__ void finish_row(const SegArgs &a, int n,
     }
 }
 
-// Chunk part (blocks [0, chunk_blocks)): one wave per chunk of 64 sorted
-// samples of one mode; lane l holds sample i0 + l with its whole gradient
-// row. A segmented inclusive scan across the lanes (Hillis-Steele, steps
-// 1..32; a lane adds the value d lanes below when that lane belongs to its
-// segment) leaves every row's sum in the lane of its last sample, which
-// finishes the row -- unless the row's samples cross a chunk edge.
-// Crossing part (the remaining blocks): one 1024-thread block per crossing
-// row, from the builder's list; thread t sums samples t, t+1024, ... (four
-// loads in flight), a fixed butterfly adds each wave's lanes and thread 0
-// adds the 16 wave sums in order. No block depends on another and
-// every addition order is fixed by the data, so results are reproducible.
-constexpr int kSegThreads = 1024;      // 16 waves: 16 chunks, or one row
-constexpr int kSegUnroll = 4;
+template <int J4>
+__device__ __forceinline__ void load_av(const SegArgs &a, int n, uint32_t row,
+                                        float (&av)[J4]) {
+    if (a.apply != 2) {
+        load_row_part<J4>(a.A[n] + (int64_t)row * J4, av);
+    } else {
+#pragma unroll
+        for (int j = 0; j < J4; ++j) av[j] = 0.f;
+    }
+}
+
+template <int J4>
+__device__ __forceinline__ void finish_row(const SegArgs &a, int n,
+                                           uint32_t row, const float (&g)[J4],
+                                           int cnt, int start) {
+    float av[J4];
+    load_av<J4>(a, n, row, av);
+    finish_row_av<J4>(a, n, row, g, cnt, start, av);
+}
+
+// One launch, three kinds of blocks (1024 threads each), longest work first
+// so that it starts at once:
+//  * long crossing rows (blocks [0, large_blocks)): one block per row of
+//    more than kSmallCross samples, from the back of the builder's list;
+//  * chunks (the next chunk_blocks): one wave per chunk of 64 sorted
+//    samples of one mode; lane l holds sample i0 + l with its whole gradient
+//    row. A segmented inclusive scan across the lanes (Hillis-Steele, steps
+//    1..32; a lane adds the value d lanes below when that lane belongs to its
+//    segment) leaves every row's sum in the lane of its last sample, which
+//    finishes the row -- unless the row's samples cross a chunk edge. The
+//    finishing lanes fetch their rows of A together with the gradient rows;
+//  * short crossing rows (the rest): one wave per row of at most kSmallCross
+//    samples, 16 per block, from the front of the list.
+// A crossing row's threads sum its samples with a fixed stride (loads issued
+// seg_unroll at a time), a fixed butterfly adds a wave and thread 0 adds a
+// block's 16 wave sums in order. No block depends on another and every
+// addition order is fixed by the data, so results are reproducible.
+constexpr int kSegThreads = 64 * kSegWaves;
+
+// loads in flight per thread: as many as the 128 registers of a 1024-thread
+// block allow
+constexpr int seg_unroll(int J4) { return J4 <= 16 ? 4 : (J4 <= 20 ? 2 : 1); }
+
+// Sum of the gradient rows [se.x, se.y) of mode n (contiguous in the sorted
+// order), thread t of a group of `stride` taking rows t, t + stride, ...,
+// then a fixed butterfly over the 64 lanes of the wave.
+template <int J4>
+__device__ __forceinline__ void sum_rows_strided(const SegArgs &a, int n,
+                                                 int4 se, int t, int stride,
+                                                 float (&acc)[J4]) {
+    constexpr int U = seg_unroll(J4);
+#pragma unroll
+    for (int q = 0; q < J4; ++q) acc[q] = 0.f;
+    const float *G = a.G + (int64_t)n * a.m * J4;
+    for (int i = se.x + t; i < se.y; i += stride * U) {
+        float g[U][J4];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int iu = i + u * stride;
+            if (iu < se.y) {
+                load_row_part<J4>(G + (int64_t)iu * J4, g[u]);
+            } else {
+#pragma unroll
+                for (int q = 0; q < J4; ++q) g[u][q] = 0.f;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int q = 0; q < J4; ++q) acc[q] += g[u][q];
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1)
+#pragma unroll
+        for (int q = 0; q < J4; ++q) acc[q] += __shfl_xor(acc[q], d);
+}
+
+// Entry k of one size class (cls 0: short, 1: long) over the modes in order:
+// returns the mode (N if k is past the last entry) and leaves the index
+// within that mode's class in k.
+__device__ __forceinline__ int find_mode(const SegArgs &a, int cls, int &k) {
+    if (a.host_counts) {
+        const int *pre = cls ? a.xl : a.xs;
+        int n = 0;
+        while (n < a.N && k >= pre[n + 1]) ++n;
+        if (n < a.N) k -= pre[n];
+        return n;
+    }
+    int n = 0;
+    while (n < a.N && k >= a.xcount[2 * n + cls]) k -= a.xcount[2 * n++ + cls];
+    return n;
+}
 
 template <int KQ>
 __global__ __launch_bounds__(kSegThreads) void seg_reduce_kernel(
     SegArgs a, int chunk_blocks) {
     constexpr int J4 = 4 * KQ;
-    __shared__ float red[kSegThreads / 64][J4 + 1];
-    if ((int)blockIdx.x >= chunk_blocks) {
-        // crossing row j of this minibatch, listed mode after mode
-        int j = blockIdx.x - chunk_blocks, n = 0;
-        while (n < a.N && j >= a.xcount[n]) j -= a.xcount[n++];
-        if (n == a.N) return;                    // surplus block
-        const int2 se = a.xlist[n][j];
-        const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    __shared__ float red[kSegWaves][J4 + 1];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    int j = blockIdx.x;
+    if (j < a.large_blocks) {
+        const int n = find_mode(a, 1, j);          // long row j (block-uniform)
+        if (n == a.N) return;
+        const int4 se = a.xlist[n][a.xcap - 1 - j];
         float acc[J4];
-#pragma unroll
-        for (int q = 0; q < J4; ++q) acc[q] = 0.f;
-        const float *G = a.G + (int64_t)n * a.m * J4;
-        for (int i = se.x + t; i < se.y; i += kSegThreads * kSegUnroll) {
-            int ps[kSegUnroll];
-#pragma unroll
-            for (int u = 0; u < kSegUnroll; ++u) {
-                const int iu = i + u * kSegThreads;
-                ps[u] = iu < se.y ? (int)a.pos[n][iu] : -1;
-            }
-            float g[kSegUnroll][J4];
-#pragma unroll
-            for (int u = 0; u < kSegUnroll; ++u) {
-                if (ps[u] >= 0) {
-                    load_row_part<J4>(G + (int64_t)ps[u] * J4, g[u]);
-                } else {
-#pragma unroll
-                    for (int q = 0; q < J4; ++q) g[u][q] = 0.f;
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < kSegUnroll; ++u)
-#pragma unroll
-                for (int q = 0; q < J4; ++q) acc[q] += g[u][q];
-        }
-#pragma unroll
-        for (int d = 32; d >= 1; d >>= 1)
-#pragma unroll
-            for (int q = 0; q < J4; ++q) acc[q] += __shfl_xor(acc[q], d);
+        sum_rows_strided<J4>(a, n, se, t, kSegThreads, acc);
         if (lane == 0)
 #pragma unroll
             for (int q = 0; q < J4; ++q) red[w][q] = acc[q];
         __syncthreads();
-        if (t == 0) {
+        if (w == 0) {
+            // lane q < J4 adds entry q of the 16 wave sums in order
+            float v = 0.f;
+            if (lane < J4)
+                for (int ww = 0; ww < kSegWaves; ++ww) v += red[ww][lane];
             float g[J4];
 #pragma unroll
-            for (int q = 0; q < J4; ++q) {
-                float v = 0.f;
-                for (int ww = 0; ww < kSegThreads / 64; ++ww) v += red[ww][q];
-                g[q] = v;
-            }
-            finish_row<J4>(a, n, a.rows[n][se.x], g, se.y - se.x, se.x);
+            for (int q = 0; q < J4; ++q) g[q] = __shfl(v, q);
+            if (lane == 0)
+                finish_row<J4>(a, n, (uint32_t)se.z, g, se.y - se.x, se.x);
         }
         return;
     }
-    const int lane = threadIdx.x & 63;
-    const int gw = blockIdx.x * (kSegThreads / 64) + (threadIdx.x >> 6);
+    j -= a.large_blocks;
+    if (j >= chunk_blocks) {
+        int k = (j - chunk_blocks) * kSegWaves + w;   // short row k
+        const int n = find_mode(a, 0, k);
+        if (n == a.N) return;                         // wave-uniform
+        const int4 se = a.xlist[n][k];
+        float acc[J4];
+        sum_rows_strided<J4>(a, n, se, lane, 64, acc);
+        if (lane == 0)
+            finish_row<J4>(a, n, (uint32_t)se.z, acc, se.y - se.x, se.x);
+        return;
+    }
+    const int gw = j * kSegWaves + w;
     if (gw >= a.N * a.nchunks) return;           // uniform per wave
     const int n = gw / a.nchunks, c = gw % a.nchunks;
     const int i0 = c * kSegChunk, i = i0 + lane;
@@ -475,45 +542,47 @@ __global__ __launch_bounds__(kSegThreads) void seg_reduce_kernel(
     const bool valid = i < i1;
     const uint32_t *rows = a.rows[n];
     const uint32_t row = valid ? rows[i] : 0xffffffffu;
+    float g[J4];
+    if (valid) {
+        load_row_part<J4>(a.G + ((int64_t)n * a.m + i) * J4, g);
+    } else {
+#pragma unroll
+        for (int q = 0; q < J4; ++q) g[q] = 0.f;
+    }
+    const uint32_t before_chunk = i0 > 0 ? rows[i0 - 1] : 0xffffffffu;
+    const uint32_t after_chunk = i1 < a.m ? rows[i1] : 0xffffffffu;
     const uint32_t below = __shfl_up(row, 1);
+    const uint32_t above = __shfl_down(row, 1);
     const bool head = lane == 0 || row != below;
     int s = head ? lane : 0;                      // first lane of my segment
 #pragma unroll
     for (int d = 1; d < 64; d <<= 1) {
-        const int t = __shfl_up(s, d);
-        if (lane >= d) s = max(s, t);
+        const int t2 = __shfl_up(s, d);
+        if (lane >= d) s = max(s, t2);
     }
-    float g[J4];
-    if (valid) {
-        load_row_part<J4>(a.G + ((int64_t)n * a.m + a.pos[n][i]) * J4, g);
-    } else {
-#pragma unroll
-        for (int j = 0; j < J4; ++j) g[j] = 0.f;
-    }
+    const bool last_in_chunk = i == i1 - 1;
+    const bool tail = valid && (last_in_chunk || above != row);
+    const bool crosses = (s == 0 && before_chunk == row) ||
+                         (last_in_chunk && after_chunk == row);
+    const bool finish = tail && !crosses;
+    float av[J4];
+    if (finish) load_av<J4>(a, n, row, av);
 #pragma unroll
     for (int d = 1; d < 64; d <<= 1) {
         const bool take = lane - d >= s;
 #pragma unroll
-        for (int j = 0; j < J4; ++j) {
-            const float t = __shfl_up(g[j], d);
-            if (take) g[j] += t;
+        for (int q = 0; q < J4; ++q) {
+            const float t2 = __shfl_up(g[q], d);
+            if (take) g[q] += t2;
         }
     }
-    const uint32_t above = __shfl_down(row, 1);
-    const bool last_in_chunk = i == i1 - 1;
-    const bool tail = valid && (last_in_chunk || above != row);
-    if (!tail) return;
-    const bool starts_before = s == 0 && i0 > 0 && rows[i0 - 1] == row;
-    const bool continues_after = last_in_chunk && i1 < a.m && rows[i1] == row;
-    if (!starts_before && !continues_after)
-        finish_row<J4>(a, n, row, g, lane - s + 1, i0 + s);
+    if (finish) finish_row_av<J4>(a, n, row, g, lane - s + 1, i0 + s, av);
 }
 
 template <int KQ>
 static hipError_t launch_seg_kq(const SegArgs &a, hipStream_t s) {
-    const int chunk_blocks =
-        (a.N * a.nchunks + kSegThreads / 64 - 1) / (kSegThreads / 64);
-    const int blocks = chunk_blocks + a.ncross;
+    const int chunk_blocks = (a.N * a.nchunks + kSegWaves - 1) / kSegWaves;
+    const int blocks = a.large_blocks + chunk_blocks + a.small_blocks;
     FT_LAUNCH(seg_reduce_kernel<KQ>, dim3(blocks), dim3(kSegThreads), 0, s, a,
               chunk_blocks);
     return hipGetLastError();

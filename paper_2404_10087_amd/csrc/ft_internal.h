@@ -37,7 +37,7 @@ constexpr int kMaxR = 32;
 constexpr int kSegChunk = 64;
 constexpr int kSmallCross = 256;      // crossing rows up to this many samples
                                       // are reduced by one wave
-constexpr int kSegWaves = 16;         // waves per row-reduction block
+constexpr int kSegWaves = 4;          // waves per row-reduction block
 
 // Mode-sorted minibatch builder: LSD radix sort, 8-bit digits, 2048-element
 // tiles aligned to minibatch starts.

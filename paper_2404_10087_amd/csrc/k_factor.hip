@@ -166,22 +166,26 @@ __global__ __launch_bounds__(kFactorThreads) void factor_grad_kernel(
     FactorArgs a, int ntiles) {
     using T = FactorTile<N, KQ, RB, BF>;
     __shared__ float sB[N * T::J4 * T::R16];
-    const float *sBm[N];
-    stage_B<N, T::J4 * T::R16>(a.B, sB, sBm);
     T tl;
-    tl.load_B(sBm);
+    tl.q = (threadIdx.x & 63) >> 4;
+    tl.c = threadIdx.x & 15;
     double loss = 0.0;
     const int nwaves = gridDim.x * (kFactorThreads / 64);
     int tile = blockIdx.x * (kFactorThreads / 64) + (threadIdx.x >> 6);
     int rows_n[N];
     RowFrag<KQ, BF> arow_n[N];
     float x_n = 0.f;
+    // the first tile's gathers are issued before B is staged, so their
+    // latency overlaps the staging and its barrier
     if (tile < ntiles) {
         const int p = tile * 16 + tl.c;
         const int ps = p < a.m ? p : a.m - 1;
         tl.gather(a.idx, a.A, a.A16, ps, rows_n, arow_n);
         x_n = a.val[ps];
     }
+    const float *sBm[N];
+    stage_B<N, T::J4 * T::R16>(a.B, sB, sBm);
+    tl.load_B(sBm);
     for (; tile < ntiles; tile += nwaves) {
         const int p = tile * 16 + tl.c;
         const bool valid = p < a.m;
@@ -419,8 +423,8 @@ __device__ __forceinline__ void finish_row(const SegArgs &a, int n,
     finish_row_av<J4>(a, n, row, g, cnt, start, av);
 }
 
-// One launch, three kinds of blocks (1024 threads each), longest work first
-// so that it starts at once:
+// One launch, three kinds of blocks (kSegWaves waves each), longest work
+// first so that it starts at once:
 //  * long crossing rows (blocks [0, large_blocks)): one block per row of
 //    more than kSmallCross samples, from the back of the builder's list;
 //  * chunks (the next chunk_blocks): one wave per chunk of 64 sorted
@@ -431,15 +435,15 @@ __device__ __forceinline__ void finish_row(const SegArgs &a, int n,
 //    finishes the row -- unless the row's samples cross a chunk edge. The
 //    finishing lanes fetch their rows of A together with the gradient rows;
 //  * short crossing rows (the rest): one wave per row of at most kSmallCross
-//    samples, 16 per block, from the front of the list.
-// A crossing row's threads sum its samples with a fixed stride (loads issued
-// seg_unroll at a time), a fixed butterfly adds a wave and thread 0 adds a
-// block's 16 wave sums in order. No block depends on another and every
-// addition order is fixed by the data, so results are reproducible.
+//    samples, kSegWaves per block, from the front of the list.
+// A crossing row's threads sum its (contiguous) gradient rows with a fixed
+// stride, seg_unroll rows loaded before they are added; a fixed butterfly
+// adds a wave and wave 0 adds a block's wave sums in order.
+// No block depends on another and every addition order is fixed by the
+// data, so results are reproducible.
 constexpr int kSegThreads = 64 * kSegWaves;
 
-// loads in flight per thread: as many as the 128 registers of a 1024-thread
-// block allow
+// rows loaded per thread before they are added
 constexpr int seg_unroll(int J4) { return J4 <= 16 ? 4 : (J4 <= 20 ? 2 : 1); }
 
 // Sum of the gradient rows [se.x, se.y) of mode n (contiguous in the sorted
@@ -510,7 +514,7 @@ __global__ __launch_bounds__(kSegThreads) void seg_reduce_kernel(
             for (int q = 0; q < J4; ++q) red[w][q] = acc[q];
         __syncthreads();
         if (w == 0) {
-            // lane q < J4 adds entry q of the 16 wave sums in order
+            // lane q < J4 adds entry q of the wave sums in order
             float v = 0.f;
             if (lane < J4)
                 for (int ww = 0; ww < kSegWaves; ++ww) v += red[ww][lane];

@@ -110,6 +110,8 @@ def main():
     ap.add_argument("--config", default="c1")
     ap.add_argument("--cpu-sample", type=int, default=46 * 65536)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-low-precision", action="store_true",
+                    help="skip the BF16 and FP8 contraction runs")
     ap.add_argument("--cache-dir", default=os.environ.get("FT_SYNTH_CACHE"),
                     help="reuse the generated tensor across runs")
     ap.add_argument("--copy-calibration", type=int, default=0,
@@ -147,31 +149,39 @@ def main():
           f"{T.test_idx.shape[1]} test nonzeros in {t_gen:.1f} s",
           file=sys.stderr, flush=True)
 
-    ft = FastTucker(w.dims, w.J, w.R)
-    ft.set_options(minibatch=w.M, lr_A=w.lr_A, lr_B=w.lr_B,
-                   lambda_A=w.lam_A, lambda_B=w.lam_B,
-                   row_scale=FT_ROW_MEAN if w.row_mean else FT_ROW_SUM,
-                   shuffle_seed=w.order_seed, reshuffle_each_epoch=1)
-    ft.set_nonzeros(FT_TRAIN, T.train_idx, T.train_val)
-    ft.set_nonzeros(FT_TEST, T.test_idx, T.test_val)
-    ft.set_params(A0, B0)
-    rmse0 = ft.rmse(FT_TEST)
+    def make(precision):
+        ft = FastTucker(w.dims, w.J, w.R)
+        ft.set_options(minibatch=w.M, lr_A=w.lr_A, lr_B=w.lr_B,
+                       lambda_A=w.lam_A, lambda_B=w.lam_B,
+                       row_scale=FT_ROW_MEAN if w.row_mean else FT_ROW_SUM,
+                       shuffle_seed=w.order_seed, reshuffle_each_epoch=1,
+                       precision=precision)
+        ft.set_nonzeros(FT_TRAIN, T.train_idx, T.train_val)
+        ft.set_nonzeros(FT_TEST, T.test_idx, T.test_val)
+        ft.set_params(A0, B0)
+        return ft
 
-    for _ in range(args.warmup):
-        ft.epoch_factors()
-        ft.epoch_core()
-    # timed region: kernel events off (each epoch call returns synchronised)
-    t_factor = t_core = 0.0
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        a = time.perf_counter()
-        ft.epoch_factors()
-        b = time.perf_counter()
-        ft.epoch_core()
-        c = time.perf_counter()
-        t_factor += b - a
-        t_core += c - b
-    elapsed = time.perf_counter() - t0
+    def timed(ft):
+        """warmup, then exactly args.steps epochs (factor + core); kernel
+        events off, every epoch call returns synchronised."""
+        for _ in range(args.warmup):
+            ft.epoch_factors()
+            ft.epoch_core()
+        t_f = t_c = 0.0
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            a = time.perf_counter()
+            ft.epoch_factors()
+            b = time.perf_counter()
+            ft.epoch_core()
+            c = time.perf_counter()
+            t_f += b - a
+            t_c += c - b
+        return time.perf_counter() - t0, t_f, t_c
+
+    ft = make(0)
+    rmse0 = ft.rmse(FT_TEST)
+    elapsed, t_factor, t_core = timed(ft)
     # per-kernel durations from HIP events on the library's stream, over
     # further epochs of the same run
     ft.profile(True)
@@ -201,6 +211,24 @@ def main():
                      "avg_us": round(1000 * v[1] / max(v[0], 1), 3)}
                  for k, v in stats.items()}
 
+    # the same epochs with the low-precision contractions (same initial
+    # parameters and epoch orders), each with its own test RMSE
+    low = {}
+    for pname, pcode in (("bf16", 1), ("fp8_e4m3", 2)):
+        if args.no_low_precision:
+            break
+        del ft
+        ft = make(pcode)
+        el, tf, tc = timed(ft)
+        for _ in range(args.profile_steps):   # same epoch count as FP32
+            ft.epoch_factors()
+            ft.epoch_core()
+        low[pname] = {"value": nnz / (el / args.steps),
+                      "ms_per_step": 1000.0 * el / args.steps,
+                      "factor_nnz_per_s": nnz / (tf / args.steps),
+                      "core_nnz_per_s": nnz / (tc / args.steps),
+                      "test_rmse": ft.rmse(FT_TEST)}
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(w, T, A0, B0, min(args.cpu_sample, nnz))
@@ -227,6 +255,12 @@ def main():
         "cpu_baseline": cpu,
         "phase_ms_per_epoch": {"factor": 1000 * t_factor / args.steps,
                                "core": 1000 * t_core / args.steps},
+        "factor_nnz_per_s": nnz / (t_factor / args.steps),
+        "core_nnz_per_s": nnz / (t_core / args.steps),
+        "builder_ms_per_epoch": sum(stats[k][1] for k in
+                                    ("order", "permute", "sort"))
+        / max(stats["sort"][0], 1),
+        "low_precision": low,
         "kernels": kernel_ms,
         "test_rmse": rmse, "train_rmse": train_rmse,
         "test_rmse_initial": rmse0,

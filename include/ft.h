@@ -48,8 +48,12 @@ typedef enum { FT_TRAIN = 0, FT_TEST = 1 } ft_set;
  * RMSE are reduced in FP64). FT_BF16: factor rows are gathered from a BF16
  * shadow of A (refreshed whenever a row is updated or set), multiplied with
  * a BF16 copy of B on the matrix cores and accumulated in FP32; A and B stay
- * FP32 masters and every update is FP32. FT_BF16 needs the verify mode.
- * FT_FP8_E4M3 is declared for the format but not available (FT_EINVAL). */
+ * FP32 masters and every update is FP32. FT_FP8_E4M3: the same with an FP8
+ * (OCP e4m3) shadow of A holding one FP32 scale per row (s = max|a| / 448,
+ * codes rounded to nearest even) and B quantised per column the same way
+ * when a kernel stages it; the FP32 accumulators are multiplied by the row
+ * and column scales. Evaluation (ft_loss, ft_rmse, ft_eval) uses the
+ * contraction precision too. BF16 and FP8 need the verify mode. */
 typedef enum { FT_FP32 = 0, FT_BF16 = 1, FT_FP8_E4M3 = 2 } ft_precision;
 
 /* How a minibatch's summed row gradient is applied (Eq. (12) applied per

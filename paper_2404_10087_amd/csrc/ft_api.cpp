@@ -45,6 +45,8 @@ struct ft_handle {
     float *A[kMaxOrder] = {};
     float *B[kMaxOrder] = {};
     uint16_t *A16[kMaxOrder] = {};   // BF16 shadow (precision FT_BF16)
+    uint8_t *A8[kMaxOrder] = {};     // FP8 shadow and per-row scales
+    float *As[kMaxOrder] = {};       // (precision FT_FP8_E4M3)
 
     int64_t nnz[2] = {0, 0};
     int32_t *idx[2][kMaxOrder] = {};
@@ -248,6 +250,8 @@ static void release(ft_handle *h) {
         dfree(h->A[n]);
         dfree(h->B[n]);
         dfree(h->A16[n]);
+        dfree(h->A8[n]);
+        dfree(h->As[n]);
 
         for (int s = 0; s < 2; ++s) {
             dfree(h->idx[s][n]);
@@ -310,13 +314,15 @@ static ft_status check_options(ft_handle *h, const ft_options *o) {
         if (!std::isfinite(x) || x < 0)
             return fail(h, FT_EINVAL,
                         "learning rates and lambdas must be finite and >= 0");
-    if (o->precision != FT_FP32 && o->precision != FT_BF16)
+    if (o->precision != FT_FP32 && o->precision != FT_BF16 &&
+        o->precision != FT_FP8_E4M3)
         return fail(h, FT_EINVAL,
-                    "precision %d is not available in this build (FP32, BF16)",
+                    "precision must be FT_FP32, FT_BF16 or FT_FP8_E4M3, got %d",
                     o->precision);
-    if (o->precision == FT_BF16 && o->deterministic == 0)
+    if (o->precision != FT_FP32 && o->deterministic == 0)
         return fail(h, FT_EINVAL,
-                    "the BF16 contraction is available in verify mode only");
+                    "the BF16 and FP8 contractions are available in verify "
+                    "mode only");
     if (o->row_scale != FT_ROW_SUM && o->row_scale != FT_ROW_MEAN)
         return fail(h, FT_EINVAL, "row_scale must be FT_ROW_SUM or FT_ROW_MEAN");
     if (o->core_step != FT_CORE_PER_EPOCH &&
@@ -334,12 +340,23 @@ static ft_status check_options(ft_handle *h, const ft_options *o) {
     return FT_OK;
 }
 
-// Refresh the BF16 shadow of A^(n) from the FP32 master.
+// Refresh the low-precision shadow of A^(n) (BF16, or FP8 codes and row
+// scales) from the FP32 master.
 static ft_status refresh_shadow(ft_handle *h, int n) {
-    if (!h->sh.bf16) return FT_OK;
     const int64_t count = h->dims[n] * h->sh.J4;
-    if (!h->A16[n]) HIPCHK(h, hipMalloc(&h->A16[n], sizeof(uint16_t) * count));
-    HIPCHK(h, launch_to_bf16(h->A[n], h->A16[n], count, h->stream));
+    if (h->sh.prec == kBF16) {
+        if (!h->A16[n])
+            HIPCHK(h, hipMalloc(&h->A16[n], sizeof(uint16_t) * count));
+        HIPCHK(h, launch_to_bf16(h->A[n], h->A16[n], count, h->stream));
+    } else if (h->sh.prec == kFP8) {
+        if (!h->A8[n]) HIPCHK(h, hipMalloc(&h->A8[n], count));
+        if (!h->As[n])
+            HIPCHK(h, hipMalloc(&h->As[n], sizeof(float) * h->dims[n]));
+        HIPCHK(h, launch_to_fp8_rows(h->A[n], h->dims[n], h->sh.J4, h->A8[n],
+                                     h->As[n], h->stream));
+    } else {
+        return FT_OK;
+    }
     HIPCHK(h, hipStreamSynchronize(h->stream));
     return FT_OK;
 }
@@ -348,18 +365,20 @@ extern "C" ft_status ft_set_options(ft_handle *h, const ft_options *o) {
     CHECK_HANDLE(h);
     ft_status st = check_options(h, o);
     if (st != FT_OK) return st;
-    const bool bf = o->precision == FT_BF16;
-    if (bf && !h->sh.bf16) {
-        h->sh.bf16 = true;
+    const int prec = o->precision == FT_BF16       ? kBF16
+                     : o->precision == FT_FP8_E4M3 ? kFP8
+                                                   : kF32;
+    if (prec != h->sh.prec) {
+        const int old = h->sh.prec;
+        h->sh.prec = prec;
         for (int n = 0; n < h->N; ++n) {
             st = refresh_shadow(h, n);
             if (st != FT_OK) {
-                h->sh.bf16 = false;
+                h->sh.prec = old;
                 return st;
             }
         }
     }
-    h->sh.bf16 = bf;
     if (o->minibatch != h->opt.minibatch ||
         o->shuffle_seed != h->opt.shuffle_seed ||
         o->reshuffle_each_epoch != h->opt.reshuffle_each_epoch)
@@ -705,7 +724,9 @@ static ft_status run_minibatch(ft_handle *h, int64_t b, int apply,
     for (int n = 0; n < h->N; ++n) {
         fa.idx[n] = h->pidx[n] + off;
         fa.A[n] = h->A[n];
-        fa.A16[n] = h->sh.bf16 ? h->A16[n] : nullptr;
+        fa.A16[n] = h->sh.prec == kBF16 ? h->A16[n] : nullptr;
+        fa.A8[n] = h->sh.prec == kFP8 ? h->A8[n] : nullptr;
+        fa.As[n] = h->sh.prec == kFP8 ? h->As[n] : nullptr;
         fa.B[n] = h->B[n];
     }
     fa.val = h->pval + off;
@@ -726,7 +747,9 @@ static ft_status run_minibatch(ft_handle *h, int64_t b, int apply,
     for (int n = 0; n < h->N; ++n) {
         sa.rows[n] = h->sk[h->sort_final][n] + off;
         sa.A[n] = h->A[n];
-        sa.A16[n] = h->sh.bf16 ? h->A16[n] : nullptr;
+        sa.A16[n] = h->sh.prec == kBF16 ? h->A16[n] : nullptr;
+        sa.A8[n] = h->sh.prec == kFP8 ? h->A8[n] : nullptr;
+        sa.As[n] = h->sh.prec == kFP8 ? h->As[n] : nullptr;
         sa.xlist[n] = h->xlist + ((size_t)b * h->N + n) * h->xcap;
         sa.grad[n] = grad ? grad[n] : nullptr;
         sa.count[n] = count ? count[n] : nullptr;
@@ -928,7 +951,9 @@ static ft_status core_pass(ft_handle *h, const int32_t *const *idx,
     for (int n = 0; n < h->N; ++n) {
         ca.idx[n] = idx[n];
         ca.A[n] = h->A[n];
-        ca.A16[n] = h->sh.bf16 ? h->A16[n] : nullptr;
+        ca.A16[n] = h->sh.prec == kBF16 ? h->A16[n] : nullptr;
+        ca.A8[n] = h->sh.prec == kFP8 ? h->A8[n] : nullptr;
+        ca.As[n] = h->sh.prec == kFP8 ? h->As[n] : nullptr;
         ca.B[n] = h->B[n];
     }
     ca.val = val;
@@ -1039,7 +1064,9 @@ extern "C" ft_status ft_eval(ft_handle *h, ft_set which, double *sse,
         for (int n = 0; n < h->N; ++n) {
             ea.idx[n] = h->idx[which][n];
             ea.A[n] = h->A[n];
-            ea.A16[n] = h->sh.bf16 ? h->A16[n] : nullptr;
+            ea.A16[n] = h->sh.prec == kBF16 ? h->A16[n] : nullptr;
+            ea.A8[n] = h->sh.prec == kFP8 ? h->A8[n] : nullptr;
+            ea.As[n] = h->sh.prec == kFP8 ? h->As[n] : nullptr;
             ea.B[n] = h->B[n];
         }
         ea.val = h->val[which];

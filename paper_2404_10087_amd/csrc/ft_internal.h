@@ -49,15 +49,22 @@ constexpr int kRadix = 256;
 // Padded shape. A^(n) is stored I_n x J4 (row stride J4 = max J_n rounded up
 // to 4); B^(n) is stored J4 x R16 (R rounded up to 16). Padding is zero and
 // stays zero under every update.
+// Contraction precisions (Shape::prec, template argument P of the tiles).
+constexpr int kF32 = 0, kBF16 = 1, kFP8 = 2;
+
 struct Shape {
     int N;
     int J4;
     int R16;
-    bool bf16;   // contraction a.B from the BF16 shadow of A (FP32 accumulate)
+    int prec;    // contraction a.B: 0 FP32, 1 BF16 shadow of A, 2 FP8 e4m3
+                 // shadow with per-row scales (FP32 accumulate throughout)
 };
 
 hipError_t launch_to_bf16(const float *src, uint16_t *dst, int64_t n,
                           hipStream_t s);
+// FP8 shadow of rows x J4 floats: J4 e4m3 codes and one scale per row
+hipError_t launch_to_fp8_rows(const float *src, int64_t rows, int J4,
+                              uint8_t *dst, float *scale, hipStream_t s);
 
 // ---------------------------------------------------------------- builder
 hipError_t launch_epoch_order(uint32_t *perm, int64_t n, uint64_t key,
@@ -92,7 +99,9 @@ hipError_t launch_sort_pass(const SortPass &p, hipStream_t s);
 
 // ---------------------------------------------------------------- factor phase
 struct FactorArgs {
-    const uint16_t *A16[kMaxOrder];  // BF16 shadow of A (bf16 shapes only)
+    const uint16_t *A16[kMaxOrder];  // BF16 shadow of A (BF16 only)
+    const uint8_t *A8[kMaxOrder];    // FP8 shadow of A and its row scales
+    const float *As[kMaxOrder];      // (FP8 only)
     const int32_t *idx[kMaxOrder];  // coordinates of the minibatch (m entries)
     const float *val;
     int32_t m;
@@ -109,7 +118,9 @@ hipError_t launch_factor_grad(const Shape &sh, const FactorArgs &a, int *nblocks
 int factor_grad_blocks(int32_t m);
 
 struct HogArgs {
-    const uint16_t *A16[kMaxOrder];  // BF16 shadow of A (bf16 shapes only)
+    const uint16_t *A16[kMaxOrder];  // BF16 shadow of A (BF16 only)
+    const uint8_t *A8[kMaxOrder];    // FP8 shadow of A and its row scales
+    const float *As[kMaxOrder];      // (FP8 only)
     const int32_t *idx[kMaxOrder];   // epoch-order coordinates
     const float *val;
     int64_t count;
@@ -147,6 +158,8 @@ struct SegArgs {
     int apply;                        // 1: update A; 0: write grad/count;
                                       // 2: autograd outputs (no lambda term)
     uint16_t *A16[kMaxOrder];         // BF16 shadow refreshed on update
+    uint8_t *A8[kMaxOrder];           // FP8 shadow and row scales refreshed
+    float *As[kMaxOrder];             // on update
     float *grad[kMaxOrder];           // dense I_n x J4 (apply 0, 2; may be
                                       // null in mode 2)
     int32_t *count[kMaxOrder];        // I_n (apply == 0)
@@ -182,7 +195,9 @@ hipError_t launch_sum_blocks(const double *part, int nper, int ngroups,
 
 // ---------------------------------------------------------------- core phase
 struct CoreArgs {
-    const uint16_t *A16[kMaxOrder];  // BF16 shadow of A (bf16 shapes only)
+    const uint16_t *A16[kMaxOrder];  // BF16 shadow of A (BF16 only)
+    const uint8_t *A8[kMaxOrder];    // FP8 shadow of A and its row scales
+    const float *As[kMaxOrder];      // (FP8 only)
     const int32_t *idx[kMaxOrder];
     const float *val;
     int64_t count;
@@ -235,7 +250,9 @@ hipError_t launch_fill_zero(float *p, int64_t n, hipStream_t s);
 
 // ---------------------------------------------------------------- evaluation
 struct EvalArgs {
-    const uint16_t *A16[kMaxOrder];  // BF16 shadow of A (bf16 shapes only)
+    const uint16_t *A16[kMaxOrder];  // BF16 shadow of A (BF16 only)
+    const uint8_t *A8[kMaxOrder];    // FP8 shadow of A and its row scales
+    const float *As[kMaxOrder];      // (FP8 only)
     const int32_t *idx[kMaxOrder];
     const float *val;
     int64_t count;

@@ -28,16 +28,16 @@ int core_grad_blocks(int64_t count) {
 }
 
 // Per-tile inputs, loaded one tile ahead of the arithmetic.
-template <int N, int KQ, bool BF>
+template <int N, int KQ, int P>
 struct CoreTileIn {
-    RowFrag<KQ, BF> arow[N];   // A[s = c][KQ q .. KQ q + KQ - 1]
+    RowFrag<KQ, P> arow[N];   // A[s = c][KQ q .. KQ q + KQ - 1]
     float x[4];                // values of samples 4q + v
 };
 
-template <int N, int KQ, bool BF>
+template <int N, int KQ, int P>
 __device__ __forceinline__ void load_core_tile(const CoreArgs &a, int64_t tile,
                                                int q, int c,
-                                               CoreTileIn<N, KQ, BF> &in) {
+                                               CoreTileIn<N, KQ, P> &in) {
     constexpr int J4 = 4 * KQ;
     const int64_t base = tile * 16;
     const int64_t last = a.count - 1;
@@ -45,7 +45,8 @@ __device__ __forceinline__ void load_core_tile(const CoreArgs &a, int64_t tile,
 #pragma unroll
     for (int n = 0; n < N; ++n) {
         const int row = a.idx[n][ps];
-        in.arow[n].load(a.A[n], a.A16[n], (int64_t)row * J4 + KQ * q);
+        in.arow[n].load(RowSrc{a.A[n], a.A16[n], a.A8[n], a.As[n]}, row, J4,
+                        q);
     }
     const int64_t s0 = base + 4 * q;
     if (s0 + 3 <= last) {
@@ -63,16 +64,20 @@ __device__ __forceinline__ void load_core_tile(const CoreArgs &a, int64_t tile,
 // Waves per SIMD the register allocator is held to: four where the tile fits
 // in 128 registers without spilling (checked per shape at build time), else
 // the compiler's choice.
-constexpr int core_waves(int N, int KQ, int RB) {
+constexpr int core_waves(int N, int KQ, int RB, int P) {
+    if (P == kFP8)   // the scale shuffles need a few more registers
+        return (KQ * RB <= 4 && RB == 1 && (N <= 3 || (N == 4 && KQ <= 2)))
+                   ? 4
+                   : 1;
     return (KQ * RB <= 4 &&
             (N <= 3 || (RB == 1 && (N == 4 ? KQ <= 3 : KQ <= 1))))
                ? 4
                : 1;
 }
 
-template <int N, int KQ, int RB, bool BF>
+template <int N, int KQ, int RB, int P>
 __global__ __launch_bounds__(256)
-__attribute__((amdgpu_waves_per_eu(core_waves(N, KQ, RB)))) void
+__attribute__((amdgpu_waves_per_eu(core_waves(N, KQ, RB, P)))) void
 core_grad_kernel(CoreArgs a, int64_t ntiles) {
     constexpr int J4 = 4 * KQ;
     constexpr int R16 = 16 * RB;
@@ -87,7 +92,7 @@ core_grad_kernel(CoreArgs a, int64_t ntiles) {
                                                           : N * 16 * TP;
     float *tr = lds + wave * WAVE_LDS;
 
-    ColFrag<KQ, BF> bop[N][RB];   // B-operand: B[k = KQ*q + t][r = 16 rb + c]
+    ColFrag<KQ, P> bop[N][RB];   // B-operand: B[k = KQ*q + t][r = 16 rb + c]
 #pragma unroll
     for (int n = 0; n < N; ++n)
 #pragma unroll
@@ -107,21 +112,25 @@ core_grad_kernel(CoreArgs a, int64_t ntiles) {
     const int64_t nwaves = (int64_t)gridDim.x * 4;
     const int64_t last = a.count - 1;
     int64_t tile = (int64_t)blockIdx.x * 4 + wave;
-    CoreTileIn<N, KQ, BF> nxt;
-    if (tile < ntiles) load_core_tile<N, KQ, BF>(a, tile, q, c, nxt);
+    CoreTileIn<N, KQ, P> nxt;
+    if (tile < ntiles) load_core_tile<N, KQ, P>(a, tile, q, c, nxt);
     for (; tile < ntiles; tile += nwaves) {
-        const CoreTileIn<N, KQ, BF> cur = nxt;
+        const CoreTileIn<N, KQ, P> cur = nxt;
         if (tile + nwaves < ntiles)
-            load_core_tile<N, KQ, BF>(a, tile + nwaves, q, c, nxt);
+            load_core_tile<N, KQ, P>(a, tile + nwaves, q, c, nxt);
         const int64_t base = tile * 16;
 
         floatx4 C[N][RB];   // C[s = 4q + v][r = 16 rb + c]
 #pragma unroll
         for (int n = 0; n < N; ++n)
 #pragma unroll
-            for (int rb = 0; rb < RB; ++rb)
+            for (int rb = 0; rb < RB; ++rb) {
                 C[n][rb] = contract(cur.arow[n], bop[n][rb],
                                     floatx4{0.f, 0.f, 0.f, 0.f});
+                if constexpr (P == kFP8)
+                    C[n][rb] = fp8_scale_c(C[n][rb], bop[n][rb].s,
+                                           cur.arow[n].s, q);
+            }
         floatx4 D[N][RB];
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb) {
@@ -223,29 +232,37 @@ static int resident_blocks(const void *kernel, size_t lds) {
     return ncu * per_cu;
 }
 
-template <int N, int KQ, int RB, bool BF>
+template <int N, int KQ, int RB, int P>
 static hipError_t launch_cg(const CoreArgs &a, int blocks, hipStream_t s) {
     const int64_t ntiles = (a.count + 15) / 16;
     const int part = N * (4 * KQ) * (16 * RB);
     const int trans = N * 16 * (4 * KQ + 1);
     const size_t lds = sizeof(float) * 4 * (part > trans ? part : trans);
     const int fit = resident_blocks(
-        reinterpret_cast<const void *>(&core_grad_kernel<N, KQ, RB, BF>), lds);
+        reinterpret_cast<const void *>(&core_grad_kernel<N, KQ, RB, P>), lds);
     if (blocks > fit) blocks = fit;
     *a.blocks_used = blocks;
-    FT_LAUNCH((core_grad_kernel<N, KQ, RB, BF>), dim3(blocks),
+    FT_LAUNCH((core_grad_kernel<N, KQ, RB, P>), dim3(blocks),
                        dim3(256), lds, s, a, ntiles);
     return hipGetLastError();
+}
+
+template <int N, int KQ, int P>
+static hipError_t launch_cg_p(const Shape &sh, const CoreArgs &a, int blocks,
+                              hipStream_t s) {
+    return sh.R16 == 16 ? launch_cg<N, KQ, 1, P>(a, blocks, s)
+                        : launch_cg<N, KQ, 2, P>(a, blocks, s);
 }
 
 template <int N, int KQ>
 static hipError_t launch_cg_r(const Shape &sh, const CoreArgs &a, int blocks,
                               hipStream_t s) {
-    if (sh.bf16)
-        return sh.R16 == 16 ? launch_cg<N, KQ, 1, true>(a, blocks, s)
-                            : launch_cg<N, KQ, 2, true>(a, blocks, s);
-    return sh.R16 == 16 ? launch_cg<N, KQ, 1, false>(a, blocks, s)
-                        : launch_cg<N, KQ, 2, false>(a, blocks, s);
+    switch (sh.prec) {
+    case kF32: return launch_cg_p<N, KQ, kF32>(sh, a, blocks, s);
+    case kBF16: return launch_cg_p<N, KQ, kBF16>(sh, a, blocks, s);
+    case kFP8: return launch_cg_p<N, KQ, kFP8>(sh, a, blocks, s);
+    }
+    return hipErrorInvalidValue;
 }
 
 template <int N>

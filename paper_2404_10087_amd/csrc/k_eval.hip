@@ -16,12 +16,12 @@ int eval_blocks(int64_t count) {
     return blocks < 1 ? 1 : (int)blocks;
 }
 
-template <int N, int KQ, int RB, bool BF>
+template <int N, int KQ, int RB, int P>
 __global__ __launch_bounds__(256) void eval_kernel(EvalArgs a, int64_t ntiles) {
     constexpr int J4 = 4 * KQ;
     constexpr int R16 = 16 * RB;
     const int lane = threadIdx.x & 63, q = lane >> 4, c = lane & 15;
-    ColFrag<KQ, BF> bf[N][RB];
+    ColFrag<KQ, P> bf[N][RB];
 #pragma unroll
     for (int n = 0; n < N; ++n)
 #pragma unroll
@@ -34,11 +34,12 @@ __global__ __launch_bounds__(256) void eval_kernel(EvalArgs a, int64_t ntiles) {
         const int64_t p = tile * 16 + c;
         const bool valid = p < a.count;
         const int64_t ps = valid ? p : a.count - 1;
-        RowFrag<KQ, BF> arow[N];
+        RowFrag<KQ, P> arow[N];
 #pragma unroll
         for (int n = 0; n < N; ++n) {
             const int row = a.idx[n][ps];
-            arow[n].load(a.A[n], a.A16[n], (int64_t)row * J4 + KQ * q);
+            arow[n].load(RowSrc{a.A[n], a.A16[n], a.A8[n], a.As[n]}, row, J4,
+                         q);
         }
         float xh = 0.f;
 #pragma unroll
@@ -46,8 +47,11 @@ __global__ __launch_bounds__(256) void eval_kernel(EvalArgs a, int64_t ntiles) {
             floatx4 prod = {1.f, 1.f, 1.f, 1.f};
 #pragma unroll
             for (int n = 0; n < N; ++n) {
-                prod *= contract(bf[n][rb], arow[n],
-                                 floatx4{0.f, 0.f, 0.f, 0.f});
+                floatx4 C = contract(bf[n][rb], arow[n],
+                                     floatx4{0.f, 0.f, 0.f, 0.f});
+                if constexpr (P == kFP8)
+                    C = fp8_scale_ct(C, bf[n][rb].s, arow[n].s, q);
+                prod *= C;
             }
             xh += (prod[0] + prod[1]) + (prod[2] + prod[3]);
         }
@@ -66,22 +70,30 @@ __global__ __launch_bounds__(256) void eval_kernel(EvalArgs a, int64_t ntiles) {
     }
 }
 
-template <int N, int KQ, int RB, bool BF>
+template <int N, int KQ, int RB, int P>
 static hipError_t launch_ev(const EvalArgs &a, int blocks, hipStream_t s) {
     const int64_t ntiles = (a.count + 15) / 16;
-    FT_LAUNCH((eval_kernel<N, KQ, RB, BF>), dim3(blocks), dim3(256), 0,
+    FT_LAUNCH((eval_kernel<N, KQ, RB, P>), dim3(blocks), dim3(256), 0,
                        s, a, ntiles);
     return hipGetLastError();
+}
+
+template <int N, int KQ, int P>
+static hipError_t launch_ev_p(const Shape &sh, const EvalArgs &a, int blocks,
+                              hipStream_t s) {
+    return sh.R16 == 16 ? launch_ev<N, KQ, 1, P>(a, blocks, s)
+                        : launch_ev<N, KQ, 2, P>(a, blocks, s);
 }
 
 template <int N, int KQ>
 static hipError_t launch_ev_r(const Shape &sh, const EvalArgs &a, int blocks,
                               hipStream_t s) {
-    if (sh.bf16)
-        return sh.R16 == 16 ? launch_ev<N, KQ, 1, true>(a, blocks, s)
-                            : launch_ev<N, KQ, 2, true>(a, blocks, s);
-    return sh.R16 == 16 ? launch_ev<N, KQ, 1, false>(a, blocks, s)
-                        : launch_ev<N, KQ, 2, false>(a, blocks, s);
+    switch (sh.prec) {
+    case kF32: return launch_ev_p<N, KQ, kF32>(sh, a, blocks, s);
+    case kBF16: return launch_ev_p<N, KQ, kBF16>(sh, a, blocks, s);
+    case kFP8: return launch_ev_p<N, KQ, kFP8>(sh, a, blocks, s);
+    }
+    return hipErrorInvalidValue;
 }
 
 template <int N>
@@ -126,6 +138,40 @@ __global__ void to_bf16_kernel(const float *src, uint16_t *dst, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += stride)
         dst[i] = f2bf(src[i]);
+}
+
+// One thread per row: J4 e4m3 codes and the row's scale (the same
+// quantisation as a factor-row update).
+template <int J4>
+__global__ void to_fp8_rows_kernel(const float *src, int64_t rows,
+                                   uint8_t *dst, float *scale) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < rows;
+         r += stride) {
+        float x[J4];
+        load_row_part<J4>(src + r * J4, x);
+        quantize_row_fp8<J4>(x, dst + r * J4, scale + r);
+    }
+}
+
+hipError_t launch_to_fp8_rows(const float *src, int64_t rows, int J4,
+                              uint8_t *dst, float *scale, hipStream_t s) {
+    int64_t blocks = (rows + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    if (blocks < 1) return hipSuccess;
+    const dim3 g((int)blocks), b(256);
+    switch (J4) {
+    case 4: hipLaunchKernelGGL(to_fp8_rows_kernel<4>, g, b, 0, s, src, rows, dst, scale); break;
+    case 8: hipLaunchKernelGGL(to_fp8_rows_kernel<8>, g, b, 0, s, src, rows, dst, scale); break;
+    case 12: hipLaunchKernelGGL(to_fp8_rows_kernel<12>, g, b, 0, s, src, rows, dst, scale); break;
+    case 16: hipLaunchKernelGGL(to_fp8_rows_kernel<16>, g, b, 0, s, src, rows, dst, scale); break;
+    case 20: hipLaunchKernelGGL(to_fp8_rows_kernel<20>, g, b, 0, s, src, rows, dst, scale); break;
+    case 24: hipLaunchKernelGGL(to_fp8_rows_kernel<24>, g, b, 0, s, src, rows, dst, scale); break;
+    case 28: hipLaunchKernelGGL(to_fp8_rows_kernel<28>, g, b, 0, s, src, rows, dst, scale); break;
+    case 32: hipLaunchKernelGGL(to_fp8_rows_kernel<32>, g, b, 0, s, src, rows, dst, scale); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_to_bf16(const float *src, uint16_t *dst, int64_t n,

@@ -41,15 +41,16 @@ int factor_grad_blocks(int32_t m) {
 
 // Per-wave state and arithmetic of one 16-sample tile (shared by the
 // deterministic and the Hogwild factor kernels).
-template <int N, int KQ, int RB, bool BF>
+template <int N, int KQ, int RB, int P>
 struct FactorTile {
     static constexpr int J4 = 4 * KQ;
     static constexpr int R16 = 16 * RB;
     static constexpr int JB = (KQ + 3) / 4;   // 16-row output blocks of J4
     int q, c;
-    // A-operands: B^(n)T for the contraction over j (FP32 or BF16 packs),
+    // A-operands: B^(n)T for the contraction over j (FP32, BF16 or FP8
+    // packs),
     // B^(n) for the one over r (FP32)
-    ColFrag<KQ, BF> bf[N][RB];
+    ColFrag<KQ, P> bf[N][RB];
     float bb[N][JB][RB][4];
     floatx4 D[N][RB];
 
@@ -76,38 +77,40 @@ struct FactorTile {
     }
 
     // Gather the rows of sample ps (this lane's column).
-    __device__ __forceinline__ void gather(const int32_t *const *idx,
-                                           const float *const *A,
-                                           const uint16_t *const *A16,
-                                           int64_t ps, int *rows,
-                                           RowFrag<KQ, BF> *arow) const {
+    template <class Args>
+    __device__ __forceinline__ void gather(const Args &a, int64_t ps,
+                                           int *rows,
+                                           RowFrag<KQ, P> *arow) const {
 #pragma unroll
         for (int n = 0; n < N; ++n) {
-            rows[n] = idx[n][ps];
-            arow[n].load(A[n], A16[n], (int64_t)rows[n] * J4 + KQ * q);
+            rows[n] = a.idx[n][ps];
+            arow[n].load(RowSrc{a.A[n], a.A16[n], a.A8[n], a.As[n]}, rows[n],
+                         J4, q);
         }
     }
 
     // C^(n)T on the matrix cores, D^(n) by prefix/suffix products; returns
     // xhat of this lane's sample (all four lanes of the column hold it).
-    __device__ __forceinline__ float forward(const int32_t *const *idx,
-                                             const float *const *A,
-                                             const uint16_t *const *A16,
-                                             int64_t ps, int *rows) {
-        RowFrag<KQ, BF> arow[N];
-        gather(idx, A, A16, ps, rows, arow);
+    template <class Args>
+    __device__ __forceinline__ float forward(const Args &a, int64_t ps,
+                                             int *rows) {
+        RowFrag<KQ, P> arow[N];
+        gather(a, ps, rows, arow);
         return contract_rows(arow);
     }
 
     __device__ __forceinline__ float contract_rows(
-        const RowFrag<KQ, BF> *arow) {
+        const RowFrag<KQ, P> *arow) {
         floatx4 C[N][RB];
 #pragma unroll
         for (int n = 0; n < N; ++n)
 #pragma unroll
-            for (int rb = 0; rb < RB; ++rb)
+            for (int rb = 0; rb < RB; ++rb) {
                 C[n][rb] = contract(bf[n][rb], arow[n],
                                     floatx4{0.f, 0.f, 0.f, 0.f});
+                if constexpr (P == kFP8)
+                    C[n][rb] = fp8_scale_ct(C[n][rb], bf[n][rb].s, arow[n].s, q);
+            }
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb) {
             floatx4 pre = {1.f, 1.f, 1.f, 1.f};
@@ -161,10 +164,10 @@ __device__ __forceinline__ void stage_B(const float *const *B, float *sB,
 
 // Each wave sweeps kFactorTilesPerWave tiles and issues the next tile's
 // index and row loads before the current tile's arithmetic.
-template <int N, int KQ, int RB, bool BF>
+template <int N, int KQ, int RB, int P>
 __global__ __launch_bounds__(kFactorThreads) void factor_grad_kernel(
     FactorArgs a, int ntiles) {
-    using T = FactorTile<N, KQ, RB, BF>;
+    using T = FactorTile<N, KQ, RB, P>;
     __shared__ float sB[N * T::J4 * T::R16];
     T tl;
     tl.q = (threadIdx.x & 63) >> 4;
@@ -173,14 +176,14 @@ __global__ __launch_bounds__(kFactorThreads) void factor_grad_kernel(
     const int nwaves = gridDim.x * (kFactorThreads / 64);
     int tile = blockIdx.x * (kFactorThreads / 64) + (threadIdx.x >> 6);
     int rows_n[N];
-    RowFrag<KQ, BF> arow_n[N];
+    RowFrag<KQ, P> arow_n[N];
     float x_n = 0.f;
     // the first tile's gathers are issued before B is staged, so their
     // latency overlaps the staging and its barrier
     if (tile < ntiles) {
         const int p = tile * 16 + tl.c;
         const int ps = p < a.m ? p : a.m - 1;
-        tl.gather(a.idx, a.A, a.A16, ps, rows_n, arow_n);
+        tl.gather(a, ps, rows_n, arow_n);
         x_n = a.val[ps];
     }
     const float *sBm[N];
@@ -192,14 +195,14 @@ __global__ __launch_bounds__(kFactorThreads) void factor_grad_kernel(
         uint32_t inv[N];
 #pragma unroll
         for (int n = 0; n < N; ++n) inv[n] = valid ? a.inv[n][p] : 0u;
-        RowFrag<KQ, BF> arow[N];
+        RowFrag<KQ, P> arow[N];
 #pragma unroll
         for (int n = 0; n < N; ++n) arow[n] = arow_n[n];
         const float x = x_n;
         if (tile + nwaves < ntiles) {
             const int pn = (tile + nwaves) * 16 + tl.c;
             const int psn = pn < a.m ? pn : a.m - 1;
-            tl.gather(a.idx, a.A, a.A16, psn, rows_n, arow_n);
+            tl.gather(a, psn, rows_n, arow_n);
             x_n = a.val[psn];
         }
         const float xh = tl.contract_rows(arow);
@@ -228,7 +231,7 @@ __global__ __launch_bounds__(kFactorThreads) void factor_grad_kernel(
 // concurrent tiles race on shared rows by design. One FP64 loss per tile.
 template <int N, int KQ, int RB>
 __global__ __launch_bounds__(kFactorThreads) void hogwild_kernel(HogArgs a) {
-    using T = FactorTile<N, KQ, RB, false>;
+    using T = FactorTile<N, KQ, RB, kF32>;
     __shared__ float sB[N * T::J4 * T::R16];
     const float *sBm[N];
     stage_B<N, T::J4 * T::R16>(a.B, sB, sBm);
@@ -243,7 +246,7 @@ __global__ __launch_bounds__(kFactorThreads) void hogwild_kernel(HogArgs a) {
         const bool valid = p < a.count;
         const int64_t ps = valid ? p : a.count - 1;
         int rows[N];
-        const float xh = tl.forward(a.idx, a.A, a.A16, ps, rows);
+        const float xh = tl.forward(a, ps, rows);
         const float r = valid ? xh - a.val[ps] : 0.f;
         double tl_loss = (valid && tl.q == 0) ? 0.5 * (double)r * (double)r : 0.0;
         tl_loss = wave_sum(tl_loss);
@@ -265,22 +268,30 @@ __global__ __launch_bounds__(kFactorThreads) void hogwild_kernel(HogArgs a) {
     }
 }
 
-template <int N, int KQ, int RB, bool BF>
+template <int N, int KQ, int RB, int P>
 static hipError_t launch_fg(const FactorArgs &a, int blocks, hipStream_t s) {
     const int ntiles = (a.m + 15) / 16;
-    FT_LAUNCH((factor_grad_kernel<N, KQ, RB, BF>), dim3(blocks),
+    FT_LAUNCH((factor_grad_kernel<N, KQ, RB, P>), dim3(blocks),
                        dim3(kFactorThreads), 0, s, a, ntiles);
     return hipGetLastError();
+}
+
+template <int N, int KQ, int P>
+static hipError_t launch_fg_p(const Shape &sh, const FactorArgs &a, int blocks,
+                              hipStream_t s) {
+    return sh.R16 == 16 ? launch_fg<N, KQ, 1, P>(a, blocks, s)
+                        : launch_fg<N, KQ, 2, P>(a, blocks, s);
 }
 
 template <int N, int KQ>
 static hipError_t launch_fg_r(const Shape &sh, const FactorArgs &a, int blocks,
                               hipStream_t s) {
-    if (sh.bf16)
-        return sh.R16 == 16 ? launch_fg<N, KQ, 1, true>(a, blocks, s)
-                            : launch_fg<N, KQ, 2, true>(a, blocks, s);
-    return sh.R16 == 16 ? launch_fg<N, KQ, 1, false>(a, blocks, s)
-                        : launch_fg<N, KQ, 2, false>(a, blocks, s);
+    switch (sh.prec) {
+    case kF32: return launch_fg_p<N, KQ, kF32>(sh, a, blocks, s);
+    case kBF16: return launch_fg_p<N, KQ, kBF16>(sh, a, blocks, s);
+    case kFP8: return launch_fg_p<N, KQ, kFP8>(sh, a, blocks, s);
+    }
+    return hipErrorInvalidValue;
 }
 
 template <int N>
@@ -397,6 +408,7 @@ __device__ __forceinline__ void finish_row_av(const SegArgs &a, int n,
 #pragma unroll
             for (int j = 0; j < J4; ++j) a.A16[n][off + j] = f2bf(o[j]);
         }
+        if (a.A8[n]) quantize_row_fp8<J4>(o, a.A8[n] + off, a.As[n] + row);
     } else {
         store_row<J4>(a.grad[n] + off, o);
         a.count[n][row] = cnt;

@@ -13,6 +13,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include "ft_internal.h"
+
 namespace ft {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
@@ -29,6 +31,13 @@ __device__ __forceinline__ floatx4 mfma_16x16x16_bf16(shortx4 a, shortx4 b,
     return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
 }
 
+// FP8 (OCP e4m3) inputs, FP32 accumulation: 16x16 output, K = 32 split as 8
+// bytes per lane over the four lane quads: lane l gives A[l % 16][8(l / 16)
+// + e] and B[8(l / 16) + e][l % 16], e = 0..7 (byte e of the 64-bit operand).
+__device__ __forceinline__ floatx4 mfma_16x16x32_fp8(long a, long b, floatx4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a, b, c, 0, 0, 0);
+}
+
 // FP32 -> BF16 with round-to-nearest-even (finite inputs), and back.
 __device__ __forceinline__ uint16_t f2bf(float f) {
     uint32_t u = __float_as_uint(f);
@@ -39,32 +48,84 @@ __device__ __forceinline__ float bf2f(uint16_t h) {
     return __uint_as_float((uint32_t)h << 16);
 }
 
+// FP8 e4m3 quantisation with one FP32 scale per vector: s = max|x| / 448
+// (448 is the largest e4m3 value), q = e4m3(x * (448 / max|x|)) rounded to
+// nearest even by the hardware conversion, clamped to +-448 first; x is
+// represented as s * q. An all-zero vector gets s = 0 and zero codes.
+constexpr float kFP8Max = 448.f;
+__device__ __forceinline__ uint32_t fp8x4(float a, float b, float c, float d) {
+    const uint32_t w = __builtin_amdgcn_cvt_pk_fp8_f32(a, b, 0u, false);
+    return __builtin_amdgcn_cvt_pk_fp8_f32(c, d, w, true);
+}
+__device__ __forceinline__ float fp8_prescale(float maxabs) {
+    return maxabs > 0.f ? kFP8Max / maxabs : 0.f;
+}
+__device__ __forceinline__ float fp8_clamp(float x) {
+    return fminf(fmaxf(x, -kFP8Max), kFP8Max);
+}
+__device__ __forceinline__ float fp8_byte(uint64_t w, int e) {
+    const uint32_t h = (uint32_t)(w >> (32 * (e / 4)));
+    switch (e & 3) {
+    case 0: return __builtin_amdgcn_cvt_f32_fp8(h, 0);
+    case 1: return __builtin_amdgcn_cvt_f32_fp8(h, 1);
+    case 2: return __builtin_amdgcn_cvt_f32_fp8(h, 2);
+    default: return __builtin_amdgcn_cvt_f32_fp8(h, 3);
+    }
+}
+
+// Quantise one row of J4 floats (J4 a multiple of 4) to J4 e4m3 bytes and
+// its scale.
+template <int J4>
+__device__ __forceinline__ void quantize_row_fp8(const float (&x)[J4],
+                                                 uint8_t *dst, float *sdst) {
+    float m = 0.f;
+#pragma unroll
+    for (int j = 0; j < J4; ++j) m = fmaxf(m, fabsf(x[j]));
+    const float inv = fp8_prescale(m);
+    uint32_t *d = reinterpret_cast<uint32_t *>(dst);
+#pragma unroll
+    for (int j = 0; j < J4; j += 4)
+        d[j / 4] = fp8x4(fp8_clamp(x[j] * inv), fp8_clamp(x[j + 1] * inv),
+                         fp8_clamp(x[j + 2] * inv), fp8_clamp(x[j + 3] * inv));
+    *sdst = m / kFP8Max;
+}
+
+// Where a tile reads factor rows from: the FP32 master and the BF16 or FP8
+// (+ per-row scale) shadow of the contraction precision.
+struct RowSrc {
+    const float *A;
+    const uint16_t *A16;
+    const uint8_t *A8;
+    const float *As;
+};
+
 // One lane's share of a factor row for the contraction over j: KQ
 // consecutive entries starting at KQ*q (q = lane / 16). FP32 keeps them as
-// floats (one 16x16x4 step each); BF16 packs them four to a 16x16x16 step,
-// zero-filling the last pack.
-template <int KQ, bool BF>
+// floats (one 16x16x4 step each); BF16 packs them four to a 16x16x16 step
+// and FP8 eight to a 16x16x32 step, zero-filling the last pack. FP8 also
+// keeps the row's scale.
+template <int KQ, int P>
 struct RowFrag;
 
 template <int KQ>
-struct RowFrag<KQ, false> {
+struct RowFrag<KQ, kF32> {
     static constexpr int STEPS = KQ;
     float v[KQ];
-    __device__ __forceinline__ void load(const float *A, const uint16_t *,
-                                         int64_t off) {
-        load_row(A + off);
+    __device__ __forceinline__ void load(const RowSrc &src, int64_t row,
+                                         int J4, int q) {
+        load_row(src.A + row * J4 + KQ * q);
     }
     __device__ __forceinline__ void load_row(const float *p);
     __device__ __forceinline__ float value(int t) const { return v[t]; }
 };
 
 template <int KQ>
-struct RowFrag<KQ, true> {
+struct RowFrag<KQ, kBF16> {
     static constexpr int STEPS = (KQ + 3) / 4;
     shortx4 v[STEPS];
-    __device__ __forceinline__ void load(const float *, const uint16_t *A16,
-                                         int64_t off) {
-        const uint16_t *p = A16 + off;
+    __device__ __forceinline__ void load(const RowSrc &src, int64_t row,
+                                         int J4, int q) {
+        const uint16_t *p = src.A16 + row * J4 + KQ * q;
         if constexpr (KQ % 4 == 0) {
 #pragma unroll
             for (int u = 0; u < STEPS; ++u)
@@ -82,13 +143,39 @@ struct RowFrag<KQ, true> {
     }
 };
 
+template <int KQ>
+struct RowFrag<KQ, kFP8> {
+    static constexpr int STEPS = (KQ + 7) / 8;
+    long v[STEPS];
+    float s;
+    __device__ __forceinline__ void load(const RowSrc &src, int64_t row,
+                                         int J4, int q) {
+        const uint8_t *p = src.A8 + row * J4 + KQ * q;
+        s = src.As[row];
+        if constexpr (KQ == 8) {
+            v[0] = *reinterpret_cast<const long *>(p);
+        } else if constexpr (KQ == 4) {
+            v[0] = (long)*reinterpret_cast<const uint32_t *>(p);
+        } else {
+            uint64_t w = 0;
+#pragma unroll
+            for (int t = 0; t < KQ; ++t) w |= (uint64_t)p[t] << (8 * t);
+            v[0] = (long)w;
+        }
+    }
+    __device__ __forceinline__ float value(int t) const {
+        return s * fp8_byte((uint64_t)v[t / 8], t % 8);
+    }
+};
+
 // The matching share of a core matrix column block: entry (t) is
-// B[KQ*q + t][col], packed like RowFrag.
-template <int KQ, bool BF>
+// B[KQ*q + t][col], packed like RowFrag. FP8 quantises the whole column
+// (all J4 entries, gathered over the four lane quads) with one scale.
+template <int KQ, int P>
 struct ColFrag;
 
 template <int KQ>
-struct ColFrag<KQ, false> {
+struct ColFrag<KQ, kF32> {
     float v[KQ];
     __device__ __forceinline__ void load(const float *B, int R16, int q,
                                          int col) {
@@ -98,7 +185,7 @@ struct ColFrag<KQ, false> {
 };
 
 template <int KQ>
-struct ColFrag<KQ, true> {
+struct ColFrag<KQ, kBF16> {
     static constexpr int STEPS = (KQ + 3) / 4;
     shortx4 v[STEPS];
     __device__ __forceinline__ void load(const float *B, int R16, int q,
@@ -114,19 +201,51 @@ struct ColFrag<KQ, true> {
     }
 };
 
+template <int KQ>
+struct ColFrag<KQ, kFP8> {
+    static constexpr int STEPS = (KQ + 7) / 8;
+    long v[STEPS];
+    float s;
+    __device__ __forceinline__ void load(const float *B, int R16, int q,
+                                         int col) {
+        float x[KQ];
+        float m = 0.f;
+#pragma unroll
+        for (int t = 0; t < KQ; ++t) {
+            x[t] = B[(KQ * q + t) * R16 + col];
+            m = fmaxf(m, fabsf(x[t]));
+        }
+        m = fmaxf(m, __shfl_xor(m, 16));
+        m = fmaxf(m, __shfl_xor(m, 32));
+        const float inv = fp8_prescale(m);
+        uint64_t w = 0;
+#pragma unroll
+        for (int t = 0; t < KQ; t += 4) {
+            const float x0 = fp8_clamp(x[t] * inv);
+            const float x1 = t + 1 < KQ ? fp8_clamp(x[t + 1] * inv) : 0.f;
+            const float x2 = t + 2 < KQ ? fp8_clamp(x[t + 2] * inv) : 0.f;
+            const float x3 = t + 3 < KQ ? fp8_clamp(x[t + 3] * inv) : 0.f;
+            w |= (uint64_t)fp8x4(x0, x1, x2, x3) << (8 * t);
+        }
+        v[0] = (long)w;
+        s = m / kFP8Max;
+    }
+};
+
 // acc += X Y over the K shares of one lane (X is the A-operand, Y the
-// B-operand of the matrix-core step).
+// B-operand of the matrix-core step). For FP8 the caller applies the
+// scales (fp8_scale_ct / fp8_scale_c).
 template <int KQ>
-__device__ __forceinline__ floatx4 contract(const ColFrag<KQ, false> &x,
-                                            const RowFrag<KQ, false> &y,
+__device__ __forceinline__ floatx4 contract(const ColFrag<KQ, kF32> &x,
+                                            const RowFrag<KQ, kF32> &y,
                                             floatx4 acc) {
 #pragma unroll
     for (int t = 0; t < KQ; ++t) acc = mfma_16x16x4(x.v[t], y.v[t], acc);
     return acc;
 }
 template <int KQ>
-__device__ __forceinline__ floatx4 contract(const ColFrag<KQ, true> &x,
-                                            const RowFrag<KQ, true> &y,
+__device__ __forceinline__ floatx4 contract(const ColFrag<KQ, kBF16> &x,
+                                            const RowFrag<KQ, kBF16> &y,
                                             floatx4 acc) {
 #pragma unroll
     for (int u = 0; u < (KQ + 3) / 4; ++u)
@@ -134,20 +253,56 @@ __device__ __forceinline__ floatx4 contract(const ColFrag<KQ, true> &x,
     return acc;
 }
 template <int KQ>
-__device__ __forceinline__ floatx4 contract(const RowFrag<KQ, false> &x,
-                                            const ColFrag<KQ, false> &y,
+__device__ __forceinline__ floatx4 contract(const ColFrag<KQ, kFP8> &x,
+                                            const RowFrag<KQ, kFP8> &y,
+                                            floatx4 acc) {
+#pragma unroll
+    for (int u = 0; u < (KQ + 7) / 8; ++u)
+        acc = mfma_16x16x32_fp8(x.v[u], y.v[u], acc);
+    return acc;
+}
+template <int KQ>
+__device__ __forceinline__ floatx4 contract(const RowFrag<KQ, kF32> &x,
+                                            const ColFrag<KQ, kF32> &y,
                                             floatx4 acc) {
 #pragma unroll
     for (int t = 0; t < KQ; ++t) acc = mfma_16x16x4(x.v[t], y.v[t], acc);
     return acc;
 }
 template <int KQ>
-__device__ __forceinline__ floatx4 contract(const RowFrag<KQ, true> &x,
-                                            const ColFrag<KQ, true> &y,
+__device__ __forceinline__ floatx4 contract(const RowFrag<KQ, kBF16> &x,
+                                            const ColFrag<KQ, kBF16> &y,
                                             floatx4 acc) {
 #pragma unroll
     for (int u = 0; u < (KQ + 3) / 4; ++u)
         acc = mfma_16x16x16_bf16(x.v[u], y.v[u], acc);
+    return acc;
+}
+template <int KQ>
+__device__ __forceinline__ floatx4 contract(const RowFrag<KQ, kFP8> &x,
+                                            const ColFrag<KQ, kFP8> &y,
+                                            floatx4 acc) {
+#pragma unroll
+    for (int u = 0; u < (KQ + 7) / 8; ++u)
+        acc = mfma_16x16x32_fp8(x.v[u], y.v[u], acc);
+    return acc;
+}
+
+// Scales of an FP8 product. C^T form (rows r = 4q + v of a column block,
+// column = this lane's sample): column scale of r from lane 4q + v, row
+// scale of the lane's own sample. C form (rows = samples 4q + v, column =
+// this lane's r): the lane's own column scale, sample scales from lanes
+// 4q + v.
+__device__ __forceinline__ floatx4 fp8_scale_ct(floatx4 acc, float col_s,
+                                                float row_s, int q) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[v] *= __shfl(col_s, 4 * q + v) * row_s;
+    return acc;
+}
+__device__ __forceinline__ floatx4 fp8_scale_c(floatx4 acc, float col_s,
+                                               float row_s, int q) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[v] *= col_s * __shfl(row_s, 4 * q + v);
     return acc;
 }
 
@@ -188,7 +343,7 @@ __device__ __forceinline__ void store_row(float *p, const float (&v)[NF]) {
 }
 
 template <int KQ>
-__device__ __forceinline__ void RowFrag<KQ, false>::load_row(const float *p) {
+__device__ __forceinline__ void RowFrag<KQ, kF32>::load_row(const float *p) {
     load_row_part<KQ>(p, v);
 }
 

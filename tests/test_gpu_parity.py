@@ -15,7 +15,7 @@ import oracle
 import synth
 from paper_2404_10087_amd import (FT_CORE_PER_MINIBATCH, FT_TEST, FT_TRAIN,
                                   FastTucker, FtError)
-from tests import _ref
+from tests import _fp8, _ref
 from tests.gpu_util import EPS32, f64, minibatch_slice, rel_norm, setup
 
 pytestmark = pytest.mark.gpu
@@ -23,6 +23,7 @@ pytestmark = pytest.mark.gpu
 LOSS_RTOL = 1e-5
 GRAD_RTOL = 1e-5
 RMSE_RTOL = 1e-4
+FP8_RMSE_RTOL = 1e-2
 
 W = {
     "c0": synth.get("c0"),
@@ -414,5 +415,73 @@ def test_bf16_shadow_follows_set_params():
     r2 = ft.rmse(FT_TRAIN)
     assert r2 != r1
     assert r2 == pytest.approx(np.sqrt(osse / T.train_idx.shape[1]), rel=1e-2)
+    with pytest.raises(FtError):
+        ft.set_options(deterministic=0)
+
+
+# ----------------------------------------------------------------- FP8
+@pytest.mark.parametrize("name", ["c0", "J12_R20", "order5_J32_R32", "zipf"])
+def test_fp8_contraction_matches_emulated_quantisation(name):
+    """FP8 e4m3 contraction: every row of A is quantised with one scale per
+    row and every column of B with one scale per column (the codes and
+    scales of the format definition, tests/_fp8.py). The device's SSE and
+    SAE equal the FP64 oracle's on the dequantised parameters, before and
+    after a factor epoch, so the shadow rows rewritten by the row updates
+    are checked too."""
+    w = W[name]
+    ft, T, _, _ = setup(w)
+    ft.set_options(precision=2)
+    for step in range(2):
+        A1, B1 = ft.get_params()
+        Aq = [_fp8.quantize(a, axis=1) for a in A1]
+        Bq = [_fp8.quantize(b, axis=0) for b in B1]
+        for which, idx, val in ((FT_TRAIN, T.train_idx, T.train_val),
+                                (FT_TEST, T.test_idx, T.test_val)):
+            sse, sae = ft.eval(which)
+            osse, osae = oracle.residual_stats(Aq, Bq, idx,
+                                               val.astype(np.float64))
+            assert sse == pytest.approx(osse, rel=LOSS_RTOL)
+            assert sae == pytest.approx(osae, rel=LOSS_RTOL)
+        if step == 0:
+            ft.set_epoch_order(perm_for(w, T))
+            ft.epoch_factors()
+
+
+@pytest.mark.parametrize("name", ["c0", "zipf"])
+def test_fp8_contraction_training_tracks_oracle(name):
+    """FP8 contraction (FP32 masters, FP32 gradient product and updates):
+    after free-running alternating epochs the test RMSE stays within
+    FP8_RMSE_RTOL of the FP64 oracle's; switching back to FP32 evaluates
+    the FP32 masters exactly."""
+    w = W[name]
+    ft, T, A0, B0 = setup(w)
+    ft.set_options(precision=2)
+    A, B = f64(A0), f64(B0)
+    tv = T.train_val.astype(np.float64)
+    sv = T.test_val.astype(np.float64)
+    for ep in range(w.epochs):
+        p = perm_for(w, T, ep)
+        ft.set_epoch_order(p)
+        ft.epoch_factors()
+        ft.epoch_core()
+        oracle.factor_epoch(A, B, T.train_idx, tv, p, w.M, w.lr_A, w.lam_A,
+                            w.row_mean)
+        oracle.core_epoch(A, B, T.train_idx, tv, w.lr_B, w.lam_B)
+    osse, _ = oracle.residual_stats(A, B, T.test_idx, sv)
+    ormse, grmse = np.sqrt(osse / len(sv)), ft.rmse(FT_TEST)
+    print(f"fp8 {name}: device {grmse:.6g} oracle {ormse:.6g} "
+          f"rel {abs(grmse / ormse - 1):.3g}")
+    assert grmse == pytest.approx(ormse, rel=FP8_RMSE_RTOL)
+    ft.set_options(precision=0)
+    A1, B1 = ft.get_params()
+    gsse, _ = oracle.residual_stats(f64(A1), f64(B1), T.test_idx, sv)
+    assert ft.rmse(FT_TEST) == pytest.approx(np.sqrt(gsse / len(sv)),
+                                             rel=LOSS_RTOL)
+
+
+def test_fp8_needs_verify_mode():
+    w = W["c0"]
+    ft, _, _, _ = setup(w, with_test=False)
+    ft.set_options(precision=2)
     with pytest.raises(FtError):
         ft.set_options(deterministic=0)

@@ -31,6 +31,32 @@ struct Pending {
 };
 }  // namespace
 
+// Everything the builder makes for one epoch order.
+struct EpochBufs {
+    uint32_t *perm = nullptr;
+    int32_t *pidx[kMaxOrder] = {};
+    float *pval = nullptr;
+    uint32_t *sk[2][kMaxOrder] = {};
+    uint32_t *sv[2][kMaxOrder] = {};
+    uint32_t *inv[kMaxOrder] = {};    // sorted index of every position
+    uint32_t *counts = nullptr;
+    size_t counts_cap = 0;
+    int sort_final = 0;
+    int4 *xlist = nullptr;            // crossing rows per minibatch and mode
+    size_t xlist_cap = 0;
+    int32_t *xcount = nullptr;
+    size_t xcount_cap = 0;
+    int xcap = 1;
+    int32_t *xcount_host = nullptr;   // pinned copy of xcount
+    size_t xcount_host_cap = 0;
+    hipEvent_t ready = nullptr;       // recorded after the last builder step
+    bool pending = false;             // xcount_host not yet waited for
+    // what the set holds (valid: built for this epoch, M, seed, training set)
+    bool valid = false;
+    uint64_t epoch = 0, seed = 0, gen = 0;
+    int64_t M = 0;
+};
+
 struct ft_handle {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -52,32 +78,22 @@ struct ft_handle {
     int32_t *idx[2][kMaxOrder] = {};
     float *val[2] = {};
 
-    // epoch state
+    // epoch state: two builder buffer sets, the current epoch's and the
+    // next one's (built ahead on bstream)
     uint64_t epoch = 0;
     bool use_user_perm = false;
     uint32_t *user_perm = nullptr;
-    uint32_t *perm = nullptr;
     uint32_t *rec = nullptr;          // training records (record_words(N) words)
-    int32_t *pidx[kMaxOrder] = {};
-    float *pval = nullptr;
-    uint32_t *sk[2][kMaxOrder] = {};
-    uint32_t *sv[2][kMaxOrder] = {};
-    uint32_t *inv[kMaxOrder] = {};     // sorted index of every position
-    uint32_t *counts = nullptr;
-    size_t counts_cap = 0;
-    int sort_final = 0;
+    uint64_t train_gen = 0;           // bumped by every new training set
+    EpochBufs eb[2];
+    int cur = 0;
+    hipStream_t bstream = nullptr;    // builder-ahead stream (default priority)
     bool prepared = false;
     int64_t prepared_M = 0;
 
     // factor-phase scratch
     float *G = nullptr;
     size_t G_cap = 0;
-    int4 *xlist = nullptr;            // crossing rows per minibatch and mode
-    size_t xlist_cap = 0;
-    int32_t *xcount = nullptr;
-    size_t xcount_cap = 0;
-    int xcap = 1;
-    std::vector<int32_t> xcount_host;  // crossing rows per minibatch and mode
     double *mb_part = nullptr;
     size_t mb_part_cap = 0;
     double *mb_loss = nullptr;
@@ -140,6 +156,27 @@ static void dfree(void *p) {
     if (p) (void)hipFree(p);
 }
 
+static ft_status alloc_epoch_bufs(ft_handle *h, EpochBufs &E);
+
+static void free_epoch_bufs(EpochBufs &E) {
+    dfree(E.perm);
+    dfree(E.pval);
+    for (int n = 0; n < kMaxOrder; ++n) {
+        dfree(E.pidx[n]);
+        dfree(E.inv[n]);
+        for (int s = 0; s < 2; ++s) {
+            dfree(E.sk[s][n]);
+            dfree(E.sv[s][n]);
+        }
+    }
+    dfree(E.counts);
+    dfree(E.xlist);
+    dfree(E.xcount);
+    if (E.xcount_host) (void)hipHostFree(E.xcount_host);
+    if (E.ready) (void)hipEventDestroy(E.ready);
+    E = EpochBufs{};
+}
+
 static int64_t nminibatches(const ft_handle *h) {
     return (h->nnz[FT_TRAIN] + h->opt.minibatch - 1) / h->opt.minibatch;
 }
@@ -156,19 +193,19 @@ static hipEvent_t pool_event(ft_handle *h) {
 }
 
 // Bracketing form (several kernels in one class): markers on the stream.
-static void prof_begin(ft_handle *h, int kind) {
+static void prof_begin(ft_handle *h, int kind, hipStream_t s) {
     if (!h->prof) return;
     hipEvent_t a = pool_event(h);
     if (!a) return;
-    (void)hipEventRecord(a, h->stream);
+    (void)hipEventRecord(a, s);
     h->pending.push_back({kind, a, nullptr});
 }
 
-static void prof_end(ft_handle *h) {
+static void prof_end(ft_handle *h, hipStream_t s) {
     if (!h->prof || h->pending.empty() || h->pending.back().b) return;
     hipEvent_t b = pool_event(h);
     if (!b) return;
-    (void)hipEventRecord(b, h->stream);
+    (void)hipEventRecord(b, s);
     h->pending.back().b = b;
 }
 
@@ -186,6 +223,7 @@ static void prof_ext(ft_handle *h, int kind) {
 static ft_status prof_collect(ft_handle *h) {
     if (h->pending.empty()) return FT_OK;
     HIPCHK(h, hipStreamSynchronize(h->stream));
+    if (h->bstream) HIPCHK(h, hipStreamSynchronize(h->bstream));
     for (auto &p : h->pending) {
         if (p.b) {
             float t = 0.f;
@@ -203,8 +241,12 @@ static ft_status prof_collect(ft_handle *h) {
 
 struct Launch {
     ft_handle *h;
-    Launch(ft_handle *hh, int kind) : h(hh) { prof_begin(h, kind); }
-    ~Launch() { prof_end(h); }
+    hipStream_t s;
+    Launch(ft_handle *hh, int kind) : h(hh), s(hh->stream) { prof_begin(h, kind, s); }
+    Launch(ft_handle *hh, int kind, hipStream_t ss) : h(hh), s(ss) {
+        prof_begin(h, kind, s);
+    }
+    ~Launch() { prof_end(h, s); }
 };
 
 struct LaunchExt {
@@ -253,24 +295,16 @@ static void release(ft_handle *h) {
         dfree(h->A8[n]);
         dfree(h->As[n]);
 
-        for (int s = 0; s < 2; ++s) {
-            dfree(h->idx[s][n]);
-            dfree(h->sk[s][n]);
-            dfree(h->sv[s][n]);
-        }
-        dfree(h->inv[n]);
-        dfree(h->pidx[n]);
+        for (int s = 0; s < 2; ++s) dfree(h->idx[s][n]);
     }
+    if (h->bstream) (void)hipStreamSynchronize(h->bstream);
+    for (auto &E : h->eb) free_epoch_bufs(E);
+    if (h->bstream) (void)hipStreamDestroy(h->bstream);
     dfree(h->val[0]);
     dfree(h->val[1]);
     dfree(h->user_perm);
-    dfree(h->perm);
     dfree(h->rec);
-    dfree(h->pval);
-    dfree(h->counts);
     dfree(h->G);
-    dfree(h->xlist);
-    dfree(h->xcount);
     dfree(h->mb_part);
     dfree(h->mb_loss);
     dfree(h->tile_loss);
@@ -491,6 +525,7 @@ extern "C" ft_status ft_create(int order, const int64_t *dims,
 extern "C" ft_status ft_destroy(ft_handle *h) {
     if (!h) return FT_OK;
     (void)hipStreamSynchronize(h->stream);
+    if (h->bstream) (void)hipStreamSynchronize(h->bstream);
     release(h);
     delete h;
     return FT_OK;
@@ -524,6 +559,7 @@ extern "C" ft_status ft_set_nonzeros(ft_handle *h, ft_set which, int64_t nnz,
                         (long long)s);
 
     HIPCHK(h, hipStreamSynchronize(h->stream));
+    if (h->bstream) HIPCHK(h, hipStreamSynchronize(h->bstream));
     for (int n = 0; n < h->N; ++n) {
         dfree(h->idx[which][n]);
         h->idx[which][n] = nullptr;
@@ -546,12 +582,11 @@ extern "C" ft_status ft_set_nonzeros(ft_handle *h, ft_set which, int64_t nnz,
         h->use_user_perm = false;
         h->prepared = false;
         h->epoch = 0;
+        h->train_gen += 1;
         dfree(h->user_perm);
         h->user_perm = nullptr;
-        dfree(h->perm);
-        h->perm = nullptr;
-        dfree(h->pval);
-        h->pval = nullptr;
+        for (auto &E : h->eb) free_epoch_bufs(E);
+        h->cur = 0;
         dfree(h->rec);
         h->rec = nullptr;
         const int rw = record_words(h->N);
@@ -559,23 +594,8 @@ extern "C" ft_status ft_set_nonzeros(ft_handle *h, ft_set which, int64_t nnz,
         HIPCHK(h, launch_pack_records(h->N, h->idx[FT_TRAIN], h->val[FT_TRAIN],
                                       nnz, h->rec, rw, h->stream));
         HIPCHK(h, hipStreamSynchronize(h->stream));
-        HIPCHK(h, hipMalloc(&h->perm, sizeof(uint32_t) * nnz));
-        HIPCHK(h, hipMalloc(&h->pval, sizeof(float) * nnz));
-        for (int n = 0; n < h->N; ++n) {
-            dfree(h->pidx[n]);
-            h->pidx[n] = nullptr;
-            HIPCHK(h, hipMalloc(&h->pidx[n], sizeof(int32_t) * nnz));
-            dfree(h->inv[n]);
-            h->inv[n] = nullptr;
-            HIPCHK(h, hipMalloc(&h->inv[n], sizeof(uint32_t) * nnz));
-            for (int s = 0; s < 2; ++s) {
-                dfree(h->sk[s][n]);
-                dfree(h->sv[s][n]);
-                h->sk[s][n] = h->sv[s][n] = nullptr;
-                HIPCHK(h, hipMalloc(&h->sk[s][n], sizeof(uint32_t) * nnz));
-                HIPCHK(h, hipMalloc(&h->sv[s][n], sizeof(uint32_t) * nnz));
-            }
-        }
+        ft_status st = alloc_epoch_bufs(h, h->eb[0]);
+        if (st != FT_OK) return st;
     }
     return FT_OK;
 }
@@ -616,29 +636,49 @@ extern "C" ft_status ft_num_minibatches(const ft_handle *h, int64_t *out) {
 }
 
 // ------------------------------------------------------------------ builder
-static ft_status draw_order(ft_handle *h, uint64_t salt) {
+// The builder writes one buffer set E for the order of epoch `epoch` on
+// stream s; nothing it reads or writes is touched by the parameters, so the
+// next epoch's set can be built while the current epoch trains.
+static ft_status alloc_epoch_bufs(ft_handle *h, EpochBufs &E) {
     const int64_t nnz = h->nnz[FT_TRAIN];
-    Launch L(h, FT_K_ORDER);
+    HIPCHK(h, hipMalloc(&E.perm, sizeof(uint32_t) * nnz));
+    HIPCHK(h, hipMalloc(&E.pval, sizeof(float) * nnz));
+    for (int n = 0; n < h->N; ++n) {
+        HIPCHK(h, hipMalloc(&E.pidx[n], sizeof(int32_t) * nnz));
+        HIPCHK(h, hipMalloc(&E.inv[n], sizeof(uint32_t) * nnz));
+        for (int s = 0; s < 2; ++s) {
+            HIPCHK(h, hipMalloc(&E.sk[s][n], sizeof(uint32_t) * nnz));
+            HIPCHK(h, hipMalloc(&E.sv[s][n], sizeof(uint32_t) * nnz));
+        }
+    }
+    HIPCHK(h, hipEventCreateWithFlags(&E.ready, hipEventDisableTiming));
+    return FT_OK;
+}
+
+static ft_status draw_order(ft_handle *h, EpochBufs &E, uint64_t epoch,
+                            uint64_t salt, hipStream_t s) {
+    const int64_t nnz = h->nnz[FT_TRAIN];
+    Launch L(h, FT_K_ORDER, s);
     if (h->use_user_perm) {
-        HIPCHK(h, hipMemcpyAsync(h->perm, h->user_perm, sizeof(uint32_t) * nnz,
-                                 hipMemcpyDeviceToDevice, h->stream));
+        HIPCHK(h, hipMemcpyAsync(E.perm, h->user_perm, sizeof(uint32_t) * nnz,
+                                 hipMemcpyDeviceToDevice, s));
     } else {
-        const uint64_t e = h->opt.reshuffle_each_epoch ? h->epoch : 0;
+        const uint64_t e = h->opt.reshuffle_each_epoch ? epoch : 0;
         const uint64_t key = h->opt.shuffle_seed ^
                              (0x9e3779b97f4a7c15ull * (2 * e + 1 + 2 * salt));
-        HIPCHK(h, launch_epoch_order(h->perm, nnz, key, h->stream));
+        HIPCHK(h, launch_epoch_order(E.perm, nnz, key, s));
     }
     return FT_OK;
 }
 
-static ft_status permute_streams(ft_handle *h) {
-    Launch L(h, FT_K_PERMUTE);
-    HIPCHK(h, launch_permute(h->N, h->rec, record_words(h->N), h->perm,
-                             h->nnz[FT_TRAIN], h->pidx, h->pval, h->stream));
+static ft_status permute_streams(ft_handle *h, EpochBufs &E, hipStream_t s) {
+    Launch L(h, FT_K_PERMUTE, s);
+    HIPCHK(h, launch_permute(h->N, h->rec, record_words(h->N), E.perm,
+                             h->nnz[FT_TRAIN], E.pidx, E.pval, s));
     return FT_OK;
 }
 
-static ft_status build_minibatches(ft_handle *h) {
+static ft_status build_minibatches(ft_handle *h, EpochBufs &E, hipStream_t s) {
     const int64_t nnz = h->nnz[FT_TRAIN];
     const int64_t M = h->opt.minibatch;
     const int nseg = (int)nminibatches(h);
@@ -649,63 +689,137 @@ static ft_status build_minibatches(ft_handle *h) {
     int bits = 0;
     while ((1ll << bits) <= maxrow) ++bits;
     const int passes = bits == 0 ? 1 : (bits + 7) / 8;
-    HIPCHK(h, ensure(&h->counts, &h->counts_cap,
+    const size_t nx = (size_t)nseg * h->N * 2;
+    HIPCHK(h, ensure(&E.counts, &E.counts_cap,
                      (size_t)h->N * nseg * kRadix * tps));
-    Launch L(h, FT_K_SORT);
+    const int xcap = cross_capacity(std::min<int64_t>(M, nnz));
+    HIPCHK(h, ensure(&E.xlist, &E.xlist_cap, (size_t)nseg * h->N * xcap));
+    HIPCHK(h, ensure(&E.xcount, &E.xcount_cap, nx));
+    if (E.xcount_host_cap < nx) {
+        if (E.xcount_host) HIPCHK(h, hipHostFree(E.xcount_host));
+        E.xcount_host = nullptr;
+        E.xcount_host_cap = 0;
+        HIPCHK(h, hipHostMalloc((void **)&E.xcount_host, sizeof(int32_t) * nx,
+                                hipHostMallocDefault));
+        E.xcount_host_cap = nx;
+    }
+    Launch L(h, FT_K_SORT, s);
     SortPass p{};
     p.N = h->N;
     p.nnz = nnz;
     p.M = M;
     p.nseg = nseg;
     p.tiles_per_seg = tps;
-    p.counts = h->counts;
+    p.counts = E.counts;
     int cur = 0;
     for (int pass = 0; pass < passes; ++pass) {
         p.shift = 8 * pass;
         for (int n = 0; n < h->N; ++n) {
-            p.key_in[n] = pass == 0 ? reinterpret_cast<const uint32_t *>(h->pidx[n])
-                                    : h->sk[cur][n];
-            p.val_in[n] = pass == 0 ? nullptr : h->sv[cur][n];
-            p.key_out[n] = h->sk[pass == 0 ? 0 : cur ^ 1][n];
-            p.val_out[n] = h->sv[pass == 0 ? 0 : cur ^ 1][n];
-            p.inv_out[n] = pass == passes - 1 ? h->inv[n] : nullptr;
+            p.key_in[n] = pass == 0 ? reinterpret_cast<const uint32_t *>(E.pidx[n])
+                                    : E.sk[cur][n];
+            p.val_in[n] = pass == 0 ? nullptr : E.sv[cur][n];
+            p.key_out[n] = E.sk[pass == 0 ? 0 : cur ^ 1][n];
+            // the last pass keeps the sorted rows and the inverse; the
+            // sorted positions themselves are not needed downstream
+            p.val_out[n] = pass == passes - 1
+                               ? nullptr
+                               : E.sv[pass == 0 ? 0 : cur ^ 1][n];
+            p.inv_out[n] = pass == passes - 1 ? E.inv[n] : nullptr;
         }
         cur = pass == 0 ? 0 : cur ^ 1;
-        HIPCHK(h, launch_sort_pass(p, h->stream));
+        HIPCHK(h, launch_sort_pass(p, s));
     }
-    h->sort_final = cur;
+    E.sort_final = cur;
     CrossArgs cx{};
     cx.N = h->N;
     cx.nnz = nnz;
     cx.M = M;
     cx.nseg = nseg;
-    cx.xcap = cross_capacity(std::min<int64_t>(M, nnz));
-    for (int n = 0; n < h->N; ++n) cx.rows[n] = h->sk[cur][n];
-    HIPCHK(h, ensure(&h->xlist, &h->xlist_cap, (size_t)nseg * h->N * cx.xcap));
-    HIPCHK(h, ensure(&h->xcount, &h->xcount_cap, (size_t)nseg * h->N * 2));
-    cx.xlist = h->xlist;
-    cx.xcount = h->xcount;
-    h->xcap = cx.xcap;
-    HIPCHK(h, launch_crossing_segments(cx, h->stream));
+    cx.xcap = xcap;
+    for (int n = 0; n < h->N; ++n) cx.rows[n] = E.sk[cur][n];
+    cx.xlist = E.xlist;
+    cx.xcount = E.xcount;
+    E.xcap = xcap;
+    HIPCHK(h, launch_crossing_segments(cx, s));
     // the crossing-row counts size the reduction grids: one read-back per
-    // epoch instead of a worst-case grid per minibatch
-    h->xcount_host.resize((size_t)nseg * h->N * 2);
-    HIPCHK(h, hipMemcpyAsync(h->xcount_host.data(), h->xcount,
-                             sizeof(int32_t) * nseg * h->N * 2,
-                             hipMemcpyDeviceToHost, h->stream));
-    HIPCHK(h, hipStreamSynchronize(h->stream));
+    // epoch (waited for before the first minibatch) instead of a worst-case
+    // grid per minibatch
+    HIPCHK(h, hipMemcpyAsync(E.xcount_host, E.xcount, sizeof(int32_t) * nx,
+                             hipMemcpyDeviceToHost, s));
+    HIPCHK(h, hipEventRecord(E.ready, s));
+    E.pending = true;
+    return FT_OK;
+}
+
+static ft_status build_epoch(ft_handle *h, EpochBufs &E, uint64_t epoch,
+                             hipStream_t s) {
+    E.valid = false;
+    ft_status st = draw_order(h, E, epoch, 0, s);
+    if (st == FT_OK) st = permute_streams(h, E, s);
+    if (st == FT_OK) st = build_minibatches(h, E, s);
+    if (st != FT_OK) return st;
+    E.valid = true;
+    E.epoch = epoch;
+    E.M = h->opt.minibatch;
+    E.seed = h->opt.shuffle_seed;
+    E.gen = h->train_gen;
+    return FT_OK;
+}
+
+// Host wait for a set's crossing-row counts.
+static ft_status counts_ready(ft_handle *h, EpochBufs &E) {
+    if (E.pending) {
+        HIPCHK(h, hipEventSynchronize(E.ready));
+        E.pending = false;
+    }
     return FT_OK;
 }
 
 static ft_status prepare(ft_handle *h) {
     if (h->nnz[FT_TRAIN] < 1) return fail(h, FT_ESTATE, "no training set");
-    ft_status st = draw_order(h, 0);
-    if (st == FT_OK) st = permute_streams(h);
-    if (st == FT_OK) st = build_minibatches(h);
+    EpochBufs &E = h->eb[h->cur];
+    ft_status st = build_epoch(h, E, h->epoch, h->stream);
+    if (st == FT_OK) st = counts_ready(h, E);
     if (st != FT_OK) return st;
     h->prepared = true;
     h->prepared_M = h->opt.minibatch;
     return FT_OK;
+}
+
+// Make the current epoch's builder output current: the set built ahead if
+// it matches, else build it now.
+static ft_status acquire_epoch(ft_handle *h) {
+    EpochBufs &A = h->eb[h->cur ^ 1];
+    if (A.valid && A.epoch == h->epoch && A.M == h->opt.minibatch &&
+        A.seed == h->opt.shuffle_seed && A.gen == h->train_gen &&
+        !h->use_user_perm && h->opt.reshuffle_each_epoch) {
+        HIPCHK(h, hipStreamWaitEvent(h->stream, A.ready, 0));
+        ft_status st = counts_ready(h, A);
+        if (st != FT_OK) return st;
+        h->cur ^= 1;
+        h->prepared = true;
+        h->prepared_M = h->opt.minibatch;
+        return FT_OK;
+    }
+    return prepare(h);
+}
+
+// Build the next epoch's set on the builder stream (it only reads the
+// training records; the set it overwrites belonged to the finished epoch).
+static ft_status build_ahead(ft_handle *h) {
+    if (!h->opt.reshuffle_each_epoch || h->use_user_perm) return FT_OK;
+    if (!h->bstream)
+        HIPCHK(h, hipStreamCreateWithFlags(&h->bstream, hipStreamNonBlocking));
+    EpochBufs &A = h->eb[h->cur ^ 1];
+    if (!A.perm) {
+        ft_status st = alloc_epoch_bufs(h, A);
+        if (st != FT_OK) return st;
+    }
+    ft_status st = counts_ready(h, A);   // an unused earlier build of A
+    if (st != FT_OK) return st;
+    // the set was last read by a finished epoch (every epoch call returns
+    // synchronised), so the builder stream may overwrite it now
+    return build_epoch(h, A, h->epoch + 1, h->bstream);
 }
 
 extern "C" ft_status ft_prepare_epoch(ft_handle *h) {
@@ -720,19 +834,20 @@ static ft_status run_minibatch(ft_handle *h, int64_t b, int apply,
     const int64_t M = h->opt.minibatch;
     const int64_t off = b * M;
     const int32_t m = (int32_t)std::min<int64_t>(M, h->nnz[FT_TRAIN] - off);
+    const EpochBufs &E = h->eb[h->cur];
     FactorArgs fa{};
     for (int n = 0; n < h->N; ++n) {
-        fa.idx[n] = h->pidx[n] + off;
+        fa.idx[n] = E.pidx[n] + off;
         fa.A[n] = h->A[n];
         fa.A16[n] = h->sh.prec == kBF16 ? h->A16[n] : nullptr;
         fa.A8[n] = h->sh.prec == kFP8 ? h->A8[n] : nullptr;
         fa.As[n] = h->sh.prec == kFP8 ? h->As[n] : nullptr;
         fa.B[n] = h->B[n];
     }
-    fa.val = h->pval + off;
+    fa.val = E.pval + off;
     fa.m = m;
     fa.G = h->G;
-    for (int n = 0; n < h->N; ++n) fa.inv[n] = h->inv[n] + off;
+    for (int n = 0; n < h->N; ++n) fa.inv[n] = E.inv[n] + off;
     fa.loss_part = loss_part;
     int nb = 0;
     {
@@ -745,23 +860,23 @@ static ft_status run_minibatch(ft_handle *h, int64_t b, int apply,
     sa.m = m;
     sa.nchunks = (m + kSegChunk - 1) / kSegChunk;
     for (int n = 0; n < h->N; ++n) {
-        sa.rows[n] = h->sk[h->sort_final][n] + off;
+        sa.rows[n] = E.sk[E.sort_final][n] + off;
         sa.A[n] = h->A[n];
         sa.A16[n] = h->sh.prec == kBF16 ? h->A16[n] : nullptr;
         sa.A8[n] = h->sh.prec == kFP8 ? h->A8[n] : nullptr;
         sa.As[n] = h->sh.prec == kFP8 ? h->As[n] : nullptr;
-        sa.xlist[n] = h->xlist + ((size_t)b * h->N + n) * h->xcap;
+        sa.xlist[n] = E.xlist + ((size_t)b * h->N + n) * E.xcap;
         sa.grad[n] = grad ? grad[n] : nullptr;
         sa.count[n] = count ? count[n] : nullptr;
     }
     sa.G = h->G;
-    sa.xcount = h->xcount + (size_t)b * h->N * 2;
-    sa.xcap = h->xcap;
+    sa.xcount = E.xcount + (size_t)b * h->N * 2;
+    sa.xcap = E.xcap;
     sa.host_counts = 1;
     sa.xs[0] = sa.xl[0] = 0;
     for (int n = 0; n < h->N; ++n) {
-        sa.xs[n + 1] = sa.xs[n] + h->xcount_host[(b * h->N + n) * 2];
-        sa.xl[n + 1] = sa.xl[n] + h->xcount_host[(b * h->N + n) * 2 + 1];
+        sa.xs[n + 1] = sa.xs[n] + E.xcount_host[(b * h->N + n) * 2];
+        sa.xl[n + 1] = sa.xl[n] + E.xcount_host[(b * h->N + n) * 2 + 1];
     }
     sa.small_blocks = (sa.xs[h->N] + kSegWaves - 1) / kSegWaves;
     sa.large_blocks = sa.xl[h->N];
@@ -790,8 +905,10 @@ static ft_status alloc_factor(ft_handle *h, int64_t nmb, int nper) {
 // tiles with immediate atomic row updates (no builder, no minibatch barrier).
 static ft_status epoch_factors_fast(ft_handle *h, std::vector<double> &losses) {
     const int64_t nnz = h->nnz[FT_TRAIN];
-    ft_status st = draw_order(h, 0);
-    if (st == FT_OK) st = permute_streams(h);
+    EpochBufs &E = h->eb[h->cur];
+    E.valid = false;
+    ft_status st = draw_order(h, E, h->epoch, 0, h->stream);
+    if (st == FT_OK) st = permute_streams(h, E, h->stream);
     if (st != FT_OK) return st;
     h->prepared = false;
     const int64_t nmb = nminibatches(h);
@@ -802,11 +919,11 @@ static ft_status epoch_factors_fast(ft_handle *h, std::vector<double> &losses) {
                              h->stream));
     HogArgs ha{};
     for (int n = 0; n < h->N; ++n) {
-        ha.idx[n] = h->pidx[n];
+        ha.idx[n] = E.pidx[n];
         ha.A[n] = h->A[n];
         ha.B[n] = h->B[n];
     }
-    ha.val = h->pval;
+    ha.val = E.pval;
     ha.count = nnz;
     ha.lr = (float)h->opt.lr_A;
     ha.lam = (float)h->opt.lambda_A;
@@ -842,7 +959,7 @@ extern "C" ft_status ft_epoch_factors(ft_handle *h, double *mb_loss) {
     const bool reuse = h->prepared && !h->opt.reshuffle_each_epoch &&
                        h->prepared_M == h->opt.minibatch;
     if (!reuse) {
-        ft_status st = prepare(h);
+        ft_status st = acquire_epoch(h);
         if (st != FT_OK) return st;
     }
     const int64_t nmb = nminibatches(h);
@@ -856,6 +973,10 @@ extern "C" ft_status ft_epoch_factors(ft_handle *h, double *mb_loss) {
         st = run_minibatch(h, b, 1, h->mb_part + b * nper, nullptr, nullptr);
         if (st != FT_OK) return st;
     }
+    // the next epoch's order, permutation and sort run beside this epoch's
+    // minibatches
+    st = build_ahead(h);
+    if (st != FT_OK) return st;
     HIPCHK(h, launch_sum_blocks(h->mb_part, nper, (int)nmb, h->mb_loss,
                                 h->stream));
     std::vector<double> losses((size_t)nmb);
@@ -995,8 +1116,10 @@ extern "C" ft_status ft_epoch_core(ft_handle *h, double *loss) {
         HIPCHK(h, hipMemcpyAsync(&l, h->scal, sizeof(double),
                                  hipMemcpyDeviceToHost, h->stream));
     } else {
-        ft_status st = draw_order(h, 1);
-        if (st == FT_OK) st = permute_streams(h);
+        EpochBufs &E = h->eb[h->cur];
+        E.valid = false;
+        ft_status st = draw_order(h, E, h->epoch, 1, h->stream);
+        if (st == FT_OK) st = permute_streams(h, E, h->stream);
         if (st != FT_OK) return st;
         h->prepared = false;   // the permuted streams now hold this order
         const int64_t M = h->opt.minibatch;
@@ -1006,8 +1129,8 @@ extern "C" ft_status ft_epoch_core(ft_handle *h, double *loss) {
             const int64_t off = b * M;
             const int64_t m = std::min<int64_t>(M, nnz - off);
             const int32_t *pi[kMaxOrder] = {};
-            for (int n = 0; n < h->N; ++n) pi[n] = h->pidx[n] + off;
-            st = core_pass(h, pi, h->pval + off, m, 1, nullptr, h->mb_loss + b);
+            for (int n = 0; n < h->N; ++n) pi[n] = E.pidx[n] + off;
+            st = core_pass(h, pi, E.pval + off, m, 1, nullptr, h->mb_loss + b);
             if (st != FT_OK) return st;
         }
         HIPCHK(h, launch_sum_blocks(h->mb_loss, (int)nmb, 1, h->scal, h->stream));
@@ -1159,7 +1282,7 @@ extern "C" ft_status ft_get_epoch_order(ft_handle *h, int64_t *perm_out) {
     if (!h->prepared) return fail(h, FT_ESTATE, "no prepared epoch");
     const int64_t nnz = h->nnz[FT_TRAIN];
     std::vector<uint32_t> p((size_t)nnz);
-    HIPCHK(h, hipMemcpyAsync(p.data(), h->perm, sizeof(uint32_t) * nnz,
+    HIPCHK(h, hipMemcpyAsync(p.data(), h->eb[h->cur].perm, sizeof(uint32_t) * nnz,
                              hipMemcpyDeviceToHost, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
     for (int64_t i = 0; i < nnz; ++i) perm_out[i] = p[(size_t)i];
@@ -1175,13 +1298,21 @@ extern "C" ft_status ft_get_minibatch_sort(ft_handle *h, int64_t b, int mode,
         return fail(h, FT_EINVAL, "bad minibatch/mode/buffers");
     const int64_t off = b * h->opt.minibatch;
     const int64_t m = std::min<int64_t>(h->opt.minibatch, h->nnz[FT_TRAIN] - off);
-    HIPCHK(h, hipMemcpyAsync(pos, h->sv[h->sort_final][mode] + off,
-                             sizeof(int32_t) * m, hipMemcpyDeviceToHost,
+    // the builder keeps, per position, its sorted index; invert it here
+    std::vector<uint32_t> inv((size_t)m);
+    const EpochBufs &E = h->eb[h->cur];
+    HIPCHK(h, hipMemcpyAsync(inv.data(), E.inv[mode] + off,
+                             sizeof(uint32_t) * m, hipMemcpyDeviceToHost,
                              h->stream));
-    HIPCHK(h, hipMemcpyAsync(rows, h->sk[h->sort_final][mode] + off,
+    HIPCHK(h, hipMemcpyAsync(rows, E.sk[E.sort_final][mode] + off,
                              sizeof(int32_t) * m, hipMemcpyDeviceToHost,
                              h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
+    for (int64_t p = 0; p < m; ++p) {
+        if (inv[p] >= (uint64_t)m)
+            return fail(h, FT_EDEVICE, "inverse sort index out of range");
+        pos[inv[p]] = (int32_t)p;
+    }
     return FT_OK;
 }
 
@@ -1436,7 +1567,8 @@ extern "C" ft_status ft_mb_backward(
                                      : sk[cur] + (size_t)n * m;
             sp.val_in[n] = pass == 0 ? nullptr : sv[cur] + (size_t)n * m;
             sp.key_out[n] = sk[out] + (size_t)n * m;
-            sp.val_out[n] = sv[out] + (size_t)n * m;
+            sp.val_out[n] =
+                pass == passes - 1 ? nullptr : sv[out] + (size_t)n * m;
             sp.inv_out[n] = pass == passes - 1 ? inv + (size_t)n * m : nullptr;
         }
         HIPCHK0(launch_sort_pass(sp, s));

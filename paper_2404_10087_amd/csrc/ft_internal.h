@@ -90,7 +90,7 @@ struct SortPass {
     const uint32_t *key_in[kMaxOrder];
     const uint32_t *val_in[kMaxOrder];   // nullptr: payload = position in segment
     uint32_t *key_out[kMaxOrder];
-    uint32_t *val_out[kMaxOrder];
+    uint32_t *val_out[kMaxOrder];   // nullptr: positions not written
     uint32_t *inv_out[kMaxOrder];   // final pass only (else nullptr):
                                     // inv[seg + pos] = sorted index in seg
     uint32_t *counts;    // [N][nseg][tiles_per_seg][kRadix]

@@ -324,7 +324,7 @@ __global__ __launch_bounds__(kSortThreads) void sort_downsweep_kernel(
     const uint32_t *vals =
         p.val_in[n] ? p.val_in[n] + t.seg_start + t.tile_off : nullptr;
     uint32_t *kout = p.key_out[n] + t.seg_start;
-    uint32_t *vout = p.val_out[n] + t.seg_start;
+    uint32_t *vout = p.val_out[n] ? p.val_out[n] + t.seg_start : nullptr;
 
     uint32_t key[kSortRounds], val[kSortRounds];
     {
@@ -417,7 +417,7 @@ __global__ __launch_bounds__(kSortThreads) void sort_downsweep_kernel(
         const uint32_t d = (kk >> p.shift) & (kRadix - 1);
         const uint32_t dst = base[d] + (uint32_t)k - lstart[d];
         kout[dst] = kk;
-        vout[dst] = sval[k];
+        if (vout) vout[dst] = sval[k];
         if (inv) inv[sval[k]] = dst;
     }
 }

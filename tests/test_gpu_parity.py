@@ -485,3 +485,28 @@ def test_fp8_needs_verify_mode():
     ft.set_options(precision=2)
     with pytest.raises(FtError):
         ft.set_options(deterministic=0)
+
+
+# ----------------------------------------------------------------- builder ahead
+def test_epoch_builder_ahead_matches_injected_orders():
+    """The next epoch's order, permutation and sort are built on a second
+    stream while the current epoch trains. Epochs that use those sets give
+    bitwise the same parameters as epochs whose orders (the same
+    counter-based permutations, from their definition) are injected one by
+    one and built in line."""
+    w = W["zipf"]
+    ft1, T, _, _ = setup(w, with_test=False)
+    ft2, _, _, _ = setup(w, with_test=False)
+    for ft in (ft1, ft2):
+        ft.set_options(shuffle_seed=91, reshuffle_each_epoch=1)
+    nnz = T.train_idx.shape[1]
+    for ep in range(3):
+        ft1.epoch_factors()
+        ft1.epoch_core()
+        ft2.set_epoch_order(_ref.feistel_order(nnz, _ref.epoch_key(91, ep)))
+        ft2.epoch_factors()
+        ft2.epoch_core()
+    A1, B1 = ft1.get_params()
+    A2, B2 = ft2.get_params()
+    for a1, a2 in zip(A1 + B1, A2 + B2):
+        assert np.array_equal(a1, a2)

@@ -656,7 +656,7 @@ static ft_status alloc_epoch_bufs(ft_handle *h, EpochBufs &E) {
 }
 
 static ft_status draw_order(ft_handle *h, EpochBufs &E, uint64_t epoch,
-                            uint64_t salt, hipStream_t s) {
+                            uint64_t salt, hipStream_t s, int cap = 0) {
     const int64_t nnz = h->nnz[FT_TRAIN];
     Launch L(h, FT_K_ORDER, s);
     if (h->use_user_perm) {
@@ -666,19 +666,21 @@ static ft_status draw_order(ft_handle *h, EpochBufs &E, uint64_t epoch,
         const uint64_t e = h->opt.reshuffle_each_epoch ? epoch : 0;
         const uint64_t key = h->opt.shuffle_seed ^
                              (0x9e3779b97f4a7c15ull * (2 * e + 1 + 2 * salt));
-        HIPCHK(h, launch_epoch_order(E.perm, nnz, key, s));
+        HIPCHK(h, launch_epoch_order(E.perm, nnz, key, s, cap));
     }
     return FT_OK;
 }
 
-static ft_status permute_streams(ft_handle *h, EpochBufs &E, hipStream_t s) {
+static ft_status permute_streams(ft_handle *h, EpochBufs &E, hipStream_t s,
+                                int cap = 0) {
     Launch L(h, FT_K_PERMUTE, s);
     HIPCHK(h, launch_permute(h->N, h->rec, record_words(h->N), E.perm,
-                             h->nnz[FT_TRAIN], E.pidx, E.pval, s));
+                             h->nnz[FT_TRAIN], E.pidx, E.pval, s, cap));
     return FT_OK;
 }
 
-static ft_status build_minibatches(ft_handle *h, EpochBufs &E, hipStream_t s) {
+static ft_status build_minibatches(ft_handle *h, EpochBufs &E, hipStream_t s,
+                                   int cap = 0) {
     const int64_t nnz = h->nnz[FT_TRAIN];
     const int64_t M = h->opt.minibatch;
     const int nseg = (int)nminibatches(h);
@@ -711,6 +713,7 @@ static ft_status build_minibatches(ft_handle *h, EpochBufs &E, hipStream_t s) {
     p.nseg = nseg;
     p.tiles_per_seg = tps;
     p.counts = E.counts;
+    p.grid_cap = cap;
     int cur = 0;
     for (int pass = 0; pass < passes; ++pass) {
         p.shift = 8 * pass;
@@ -739,6 +742,7 @@ static ft_status build_minibatches(ft_handle *h, EpochBufs &E, hipStream_t s) {
     for (int n = 0; n < h->N; ++n) cx.rows[n] = E.sk[cur][n];
     cx.xlist = E.xlist;
     cx.xcount = E.xcount;
+    cx.grid_cap = cap;
     E.xcap = xcap;
     HIPCHK(h, launch_crossing_segments(cx, s));
     // the crossing-row counts size the reduction grids: one read-back per
@@ -752,11 +756,11 @@ static ft_status build_minibatches(ft_handle *h, EpochBufs &E, hipStream_t s) {
 }
 
 static ft_status build_epoch(ft_handle *h, EpochBufs &E, uint64_t epoch,
-                             hipStream_t s) {
+                             hipStream_t s, int cap = 0) {
     E.valid = false;
-    ft_status st = draw_order(h, E, epoch, 0, s);
-    if (st == FT_OK) st = permute_streams(h, E, s);
-    if (st == FT_OK) st = build_minibatches(h, E, s);
+    ft_status st = draw_order(h, E, epoch, 0, s, cap);
+    if (st == FT_OK) st = permute_streams(h, E, s, cap);
+    if (st == FT_OK) st = build_minibatches(h, E, s, cap);
     if (st != FT_OK) return st;
     E.valid = true;
     E.epoch = epoch;
@@ -806,6 +810,9 @@ static ft_status acquire_epoch(ft_handle *h) {
 
 // Build the next epoch's set on the builder stream (it only reads the
 // training records; the set it overwrites belonged to the finished epoch).
+// Its kernels run as small persistent grids so that the current epoch's
+// latency-bound minibatch kernels keep most of the workgroup slots.
+constexpr int kAheadGrid = 256;
 static ft_status build_ahead(ft_handle *h) {
     if (!h->opt.reshuffle_each_epoch || h->use_user_perm) return FT_OK;
     if (!h->bstream)
@@ -819,7 +826,7 @@ static ft_status build_ahead(ft_handle *h) {
     if (st != FT_OK) return st;
     // the set was last read by a finished epoch (every epoch call returns
     // synchronised), so the builder stream may overwrite it now
-    return build_epoch(h, A, h->epoch + 1, h->bstream);
+    return build_epoch(h, A, h->epoch + 1, h->bstream, kAheadGrid);
 }
 
 extern "C" ft_status ft_prepare_epoch(ft_handle *h) {

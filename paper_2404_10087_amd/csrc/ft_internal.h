@@ -68,7 +68,8 @@ hipError_t launch_to_fp8_rows(const float *src, int64_t rows, int J4,
 
 // ---------------------------------------------------------------- builder
 hipError_t launch_epoch_order(uint32_t *perm, int64_t n, uint64_t key,
-                              hipStream_t s);
+                              hipStream_t s,
+                              int grid_cap = 0);
 hipError_t launch_copy_order(uint32_t *perm, const int64_t *src, int64_t n,
                              hipStream_t s);
 // Training-set records: RW = 4 words (order <= 3) or 8 words (order 4..5).
@@ -78,7 +79,8 @@ hipError_t launch_pack_records(int N, const int32_t *const *idx,
                                int rw, hipStream_t s);
 hipError_t launch_permute(int N, const uint32_t *rec, int rw,
                           const uint32_t *perm, int64_t nnz,
-                          int32_t *const *pidx, float *pval, hipStream_t s);
+                          int32_t *const *pidx, float *pval, hipStream_t s,
+                          int grid_cap = 0);
 
 struct SortPass {
     int N;
@@ -94,6 +96,7 @@ struct SortPass {
     uint32_t *inv_out[kMaxOrder];   // final pass only (else nullptr):
                                     // inv[seg + pos] = sorted index in seg
     uint32_t *counts;    // [N][nseg][tiles_per_seg][kRadix]
+    int grid_cap;        // > 0: at most this many workgroups (background)
 };
 hipError_t launch_sort_pass(const SortPass &p, hipStream_t s);
 
@@ -183,6 +186,7 @@ struct CrossArgs {
     const uint32_t *rows[kMaxOrder];  // sorted rows of the whole epoch
     int4 *xlist;                      // [nseg][N][xcap]
     int32_t *xcount;                  // [nseg][N][2] (short, long rows)
+    int grid_cap;                     // > 0: at most this many workgroups
 };
 hipError_t launch_crossing_segments(const CrossArgs &c, hipStream_t s);
 inline int cross_capacity(int64_t m) {

@@ -73,7 +73,7 @@ static uint64_t host_mix64(uint64_t z) {
 }
 
 hipError_t launch_epoch_order(uint32_t *perm, int64_t n, uint64_t key,
-                              hipStream_t s) {
+                              hipStream_t s, int grid_cap) {
     if (n < 1 || n > 0x7fffffffll) return hipErrorInvalidValue;
     Feistel f;
     uint64_t st = key;
@@ -87,6 +87,7 @@ hipError_t launch_epoch_order(uint32_t *perm, int64_t n, uint64_t key,
     f.b = (uint32_t)((n + a - 1) / a);
     int blocks = (int)((n + 255) / 256);
     if (blocks > 8192) blocks = 8192;
+    if (grid_cap > 0 && blocks > grid_cap) blocks = grid_cap;
     hipLaunchKernelGGL(epoch_order_kernel, dim3(blocks), dim3(256), 0, s, perm,
                        (uint32_t)n, f);
     return hipGetLastError();
@@ -195,7 +196,8 @@ __global__ void permute_kernel(PermuteArgs a) {
 
 hipError_t launch_permute(int N, const uint32_t *rec, int rw,
                           const uint32_t *perm, int64_t nnz,
-                          int32_t *const *pidx, float *pval, hipStream_t s) {
+                          int32_t *const *pidx, float *pval, hipStream_t s,
+                          int grid_cap) {
     PermuteArgs a{};
     for (int n = 0; n < N; ++n) a.pidx[n] = pidx[n];
     a.rec = rec;
@@ -204,6 +206,7 @@ hipError_t launch_permute(int N, const uint32_t *rec, int rw,
     a.nnz = nnz;
     a.N = N;
     int blocks = (int)std::min<int64_t>((nnz + 255) / 256, 8192);
+    if (grid_cap > 0 && blocks > grid_cap) blocks = grid_cap;
     if (rw == 4)
         hipLaunchKernelGGL(permute_kernel<4>, dim3(blocks), dim3(256), 0, s, a);
     else
@@ -242,9 +245,8 @@ __device__ __forceinline__ TileInfo tile_info(const SortPass &p, int b,
 // for the surplus ids of the last group.
 constexpr int kXcds = 8;
 
-__device__ __forceinline__ bool sort_tile_of(const SortPass &p, int &tb,
+__device__ __forceinline__ bool sort_tile_of(const SortPass &p, int L, int &tb,
                                              int &b, int &n) {
-    const int L = blockIdx.x;
     const int slot = L / kXcds;
     const int sn = (slot / p.tiles_per_seg) * kXcds + L % kXcds;
     if (sn >= p.nseg * p.N) return false;
@@ -254,7 +256,7 @@ __device__ __forceinline__ bool sort_tile_of(const SortPass &p, int &tb,
     return true;
 }
 
-static int sort_grid(const SortPass &p) {
+__host__ __device__ inline int sort_grid(const SortPass &p) {
     const int groups = (p.nseg * p.N + kXcds - 1) / kXcds;
     return groups * kXcds * p.tiles_per_seg;
 }
@@ -266,11 +268,11 @@ __device__ __forceinline__ uint32_t *counts_at(const SortPass &p, int n, int b,
                           kRadix;
 }
 
-// One block per tile (sort_tile_of). Digit histogram of one tile; every wave
-// counts into its own LDS histogram so hot rows contend only within a wave.
-__global__ __launch_bounds__(kSortThreads) void sort_upsweep_kernel(SortPass p) {
+// Digit histogram of tile id L (sort_tile_of); every wave counts into its
+// own LDS histogram so hot rows contend only within a wave.
+__device__ __forceinline__ void upsweep_tile(const SortPass &p, int L) {
     int tb, b, n;
-    if (!sort_tile_of(p, tb, b, n)) return;
+    if (!sort_tile_of(p, L, tb, b, n)) return;
     TileInfo t = tile_info(p, b, tb);
     if (t.tile_len == 0) return;
     constexpr int W = kSortThreads / 64;
@@ -295,7 +297,17 @@ __global__ __launch_bounds__(kSortThreads) void sort_upsweep_kernel(SortPass p) 
     counts_at(p, n, b, tb)[threadIdx.x] = c;
 }
 
-// One block per tile (sort_tile_of). Stable scatter, staged in LDS. The global
+// Tile ids blockIdx.x, blockIdx.x + gridDim.x, ... (gridDim.x a multiple of
+// kXcds keeps every id on its block's XCD).
+__global__ __launch_bounds__(kSortThreads) void sort_upsweep_kernel(SortPass p) {
+    const int total = sort_grid(p);
+    for (int L = blockIdx.x; L < total; L += gridDim.x) {
+        upsweep_tile(p, L);
+        __syncthreads();
+    }
+}
+
+// Stable scatter of tile id L (sort_tile_of), staged in LDS. The global
 // start of digit d for this tile is the exclusive scan over digits of the
 // segment's digit totals plus the counts of d in the tiles before this one
 // (read from the upsweep's histograms). The tile is then ordered by digit
@@ -306,10 +318,9 @@ __global__ __launch_bounds__(kSortThreads) void sort_upsweep_kernel(SortPass p) 
 // positions of one digit's run. The final pass also records, for every
 // in-minibatch position, its sorted index (the factor kernel writes each
 // sample's gradient rows straight to their sorted slots).
-__global__ __launch_bounds__(kSortThreads) void sort_downsweep_kernel(
-    SortPass p) {
+__device__ __forceinline__ void downsweep_tile(const SortPass &p, int L) {
     int tb, b, n;
-    if (!sort_tile_of(p, tb, b, n)) return;
+    if (!sort_tile_of(p, L, tb, b, n)) return;
     TileInfo t = tile_info(p, b, tb);
     if (t.tile_len == 0) return;
     __shared__ uint32_t base[kRadix];     // global start of digit d (this tile)
@@ -422,6 +433,15 @@ __global__ __launch_bounds__(kSortThreads) void sort_downsweep_kernel(
     }
 }
 
+__global__ __launch_bounds__(kSortThreads) void sort_downsweep_kernel(
+    SortPass p) {
+    const int total = sort_grid(p);
+    for (int L = blockIdx.x; L < total; L += gridDim.x) {
+        downsweep_tile(p, L);
+        __syncthreads();
+    }
+}
+
 // ------------------------------------------------------------------ crossings
 // One block per minibatch and mode, one thread per chunk edge q = k kSegChunk
 // (k = 1 .. xcap, in rounds of kCrossThreads edges). A thread whose edge is
@@ -434,9 +454,8 @@ __global__ __launch_bounds__(kSortThreads) void sort_downsweep_kernel(
 // on every run.
 constexpr int kCrossThreads = 1024;
 
-__global__ __launch_bounds__(kCrossThreads) void crossing_segments_kernel(
-    CrossArgs c) {
-    const int b = blockIdx.x, n = blockIdx.y;
+__device__ __forceinline__ void crossing_one(const CrossArgs &c, int b,
+                                             int n) {
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     constexpr int W = kCrossThreads / 64;
     __shared__ int wtot[2][W];
@@ -506,14 +525,28 @@ __global__ __launch_bounds__(kCrossThreads) void crossing_segments_kernel(
     }
 }
 
+// (minibatch, mode) pairs blockIdx.x, blockIdx.x + gridDim.x, ...
+__global__ __launch_bounds__(kCrossThreads) void crossing_segments_kernel(
+    CrossArgs c) {
+    for (int id = blockIdx.x; id < c.nseg * c.N; id += gridDim.x) {
+        crossing_one(c, id / c.N, id % c.N);
+        __syncthreads();
+    }
+}
+
 hipError_t launch_crossing_segments(const CrossArgs &c, hipStream_t s) {
-    hipLaunchKernelGGL(crossing_segments_kernel, dim3(c.nseg, c.N),
+    int blocks = c.nseg * c.N;
+    if (c.grid_cap > 0 && blocks > c.grid_cap) blocks = c.grid_cap;
+    hipLaunchKernelGGL(crossing_segments_kernel, dim3(blocks),
                        dim3(kCrossThreads), 0, s, c);
     return hipGetLastError();
 }
 
 hipError_t launch_sort_pass(const SortPass &p, hipStream_t s) {
-    dim3 g3(sort_grid(p));
+    int grid = sort_grid(p);
+    if (p.grid_cap > 0 && grid > p.grid_cap)
+        grid = (p.grid_cap + kXcds - 1) / kXcds * kXcds;
+    dim3 g3(grid);
     hipLaunchKernelGGL(sort_upsweep_kernel, g3, dim3(kSortThreads), 0, s, p);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

@@ -111,7 +111,7 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=46 * 65536)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-low-precision", action="store_true",
-                    help="skip the BF16 and FP8 contraction runs")
+                    help="skip the BF16, FP8 and Hogwild comparison runs")
     ap.add_argument("--cache-dir", default=os.environ.get("FT_SYNTH_CACHE"),
                     help="reuse the generated tensor across runs")
     ap.add_argument("--copy-calibration", type=int, default=0,
@@ -136,11 +136,13 @@ def main():
 
     import synth
     from paper_2404_10087_amd import (FT_ROW_MEAN, FT_ROW_SUM, FT_TEST,
-                                      FT_TRAIN, FastTucker)
+                                      FT_TRAIN, FastTucker, FtError)
 
     w = synth.get(args.config)
     t_gen = time.perf_counter()
-    T = synth.make_tensor(w, cache_dir=args.cache_dir)
+    T = synth.make_tensor(
+        w, cache_dir=args.cache_dir,
+        progress=lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True))
     A0, B0 = synth.init_params(w.init_seed, w.dims, w.J, w.R, w.init_a_std,
                                w.init_b_std, w.init_dist)
     t_gen = time.perf_counter() - t_gen
@@ -211,18 +213,27 @@ def main():
                      "avg_us": round(1000 * v[1] / max(v[0], 1), 3)}
                  for k, v in stats.items()}
 
-    # the same epochs with the low-precision contractions (same initial
-    # parameters and epoch orders), each with its own test RMSE
+    # the same epochs with the low-precision contractions and with the
+    # Hogwild fast mode (same initial parameters and epoch orders), each with
+    # its own test RMSE
     low = {}
-    for pname, pcode in (("bf16", 1), ("fp8_e4m3", 2)):
+    for pname, pcode in (("bf16", 1), ("fp8_e4m3", 2), ("hogwild_fp32", 0)):
         if args.no_low_precision:
             break
         del ft
         ft = make(pcode)
-        el, tf, tc = timed(ft)
-        for _ in range(args.profile_steps):   # same epoch count as FP32
-            ft.epoch_factors()
-            ft.epoch_core()
+        if pname.startswith("hogwild"):
+            # the paper's execution model: no minibatch barrier, atomic
+            # per-tile row updates (not reproducible; for comparison only)
+            ft.set_options(deterministic=0)
+        try:
+            el, tf, tc = timed(ft)
+            for _ in range(args.profile_steps):   # same epoch count as FP32
+                ft.epoch_factors()
+                ft.epoch_core()
+        except FtError as e:     # e.g. a Hogwild run that diverges
+            low[pname] = {"error": str(e)}
+            continue
         low[pname] = {"value": nnz / (el / args.steps),
                       "ms_per_step": 1000.0 * el / args.steps,
                       "factor_nnz_per_s": nnz / (tf / args.steps),

@@ -93,7 +93,7 @@ typedef enum {
     FT_K_SORT = 2,         /* mode-sorted minibatch builder (all passes)     */
     FT_K_FACTOR_GRAD = 3,  /* gather + contract + Hadamard + residual + grad */
     FT_K_SEG_REDUCE = 4,   /* sorted segmented reduction + row update        */
-    FT_K_SEG_FIXUP = 5,    /* rows whose samples span several chunks        */
+    FT_K_SEG_COMBINE = 5,  /* long rows summed in several parts             */
     FT_K_CORE_GRAD = 6,    /* core-gradient partials                         */
     FT_K_CORE_UPDATE = 7,  /* fixed-order partial sum + core update          */
     FT_K_EVAL = 8,         /* forward-only residual statistics               */

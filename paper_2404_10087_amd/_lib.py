@@ -17,7 +17,7 @@ FT_FP32, FT_BF16, FT_FP8_E4M3 = 0, 1, 2
 FT_ROW_SUM, FT_ROW_MEAN = 0, 1
 FT_CORE_PER_EPOCH, FT_CORE_PER_MINIBATCH = 0, 1
 KERNELS = ["order", "permute", "sort", "factor_grad", "seg_reduce",
-           "seg_fixup", "core_grad", "core_update", "eval", "hogwild"]
+           "seg_combine", "core_grad", "core_update", "eval", "hogwild"]
 
 
 class Options(C.Structure):

@@ -44,9 +44,12 @@ struct EpochBufs {
     int sort_final = 0;
     int4 *xlist = nullptr;            // crossing rows per minibatch and mode
     size_t xlist_cap = 0;
-    int32_t *xcount = nullptr;
+    int4 *plist = nullptr;            // their parts of kPartRows samples
+    size_t plist_cap = 0;
+    int32_t *xcount = nullptr;        // kXCounts per minibatch and mode
     size_t xcount_cap = 0;
     int xcap = 1;
+    int pcap = 1;
     int32_t *xcount_host = nullptr;   // pinned copy of xcount
     size_t xcount_host_cap = 0;
     hipEvent_t ready = nullptr;       // recorded after the last builder step
@@ -94,6 +97,8 @@ struct ft_handle {
     // factor-phase scratch
     float *G = nullptr;
     size_t G_cap = 0;
+    float *P = nullptr;               // part sums of long rows
+    size_t P_cap = 0;
     double *mb_part = nullptr;
     size_t mb_part_cap = 0;
     double *mb_loss = nullptr;
@@ -171,6 +176,7 @@ static void free_epoch_bufs(EpochBufs &E) {
     }
     dfree(E.counts);
     dfree(E.xlist);
+    dfree(E.plist);
     dfree(E.xcount);
     if (E.xcount_host) (void)hipHostFree(E.xcount_host);
     if (E.ready) (void)hipEventDestroy(E.ready);
@@ -305,6 +311,7 @@ static void release(ft_handle *h) {
     dfree(h->user_perm);
     dfree(h->rec);
     dfree(h->G);
+    dfree(h->P);
     dfree(h->mb_part);
     dfree(h->mb_loss);
     dfree(h->tile_loss);
@@ -691,11 +698,13 @@ static ft_status build_minibatches(ft_handle *h, EpochBufs &E, hipStream_t s,
     int bits = 0;
     while ((1ll << bits) <= maxrow) ++bits;
     const int passes = bits == 0 ? 1 : (bits + 7) / 8;
-    const size_t nx = (size_t)nseg * h->N * 2;
+    const size_t nx = (size_t)nseg * h->N * kXCounts;
     HIPCHK(h, ensure(&E.counts, &E.counts_cap,
                      (size_t)h->N * nseg * kRadix * tps));
     const int xcap = cross_capacity(std::min<int64_t>(M, nnz));
+    const int pcap = part_capacity(std::min<int64_t>(M, nnz));
     HIPCHK(h, ensure(&E.xlist, &E.xlist_cap, (size_t)nseg * h->N * xcap));
+    HIPCHK(h, ensure(&E.plist, &E.plist_cap, (size_t)nseg * h->N * pcap));
     HIPCHK(h, ensure(&E.xcount, &E.xcount_cap, nx));
     if (E.xcount_host_cap < nx) {
         if (E.xcount_host) HIPCHK(h, hipHostFree(E.xcount_host));
@@ -741,9 +750,12 @@ static ft_status build_minibatches(ft_handle *h, EpochBufs &E, hipStream_t s,
     cx.xcap = xcap;
     for (int n = 0; n < h->N; ++n) cx.rows[n] = E.sk[cur][n];
     cx.xlist = E.xlist;
+    cx.plist = E.plist;
+    cx.pcap = pcap;
     cx.xcount = E.xcount;
     cx.grid_cap = cap;
     E.xcap = xcap;
+    E.pcap = pcap;
     HIPCHK(h, launch_crossing_segments(cx, s));
     // the crossing-row counts size the reduction grids: one read-back per
     // epoch (waited for before the first minibatch) instead of a worst-case
@@ -873,20 +885,29 @@ static ft_status run_minibatch(ft_handle *h, int64_t b, int apply,
         sa.A8[n] = h->sh.prec == kFP8 ? h->A8[n] : nullptr;
         sa.As[n] = h->sh.prec == kFP8 ? h->As[n] : nullptr;
         sa.xlist[n] = E.xlist + ((size_t)b * h->N + n) * E.xcap;
+        sa.plist[n] = E.plist + ((size_t)b * h->N + n) * E.pcap;
         sa.grad[n] = grad ? grad[n] : nullptr;
         sa.count[n] = count ? count[n] : nullptr;
     }
     sa.G = h->G;
-    sa.xcount = E.xcount + (size_t)b * h->N * 2;
+    sa.xcount = E.xcount + (size_t)b * h->N * kXCounts;
     sa.xcap = E.xcap;
+    sa.pcap = E.pcap;
+    sa.P = h->P;
     sa.host_counts = 1;
-    sa.xs[0] = sa.xl[0] = 0;
+    sa.xs[0] = sa.xl[0] = sa.xp[0] = 0;
+    int nmulti = 0;
     for (int n = 0; n < h->N; ++n) {
-        sa.xs[n + 1] = sa.xs[n] + E.xcount_host[(b * h->N + n) * 2];
-        sa.xl[n + 1] = sa.xl[n] + E.xcount_host[(b * h->N + n) * 2 + 1];
+        const int32_t *xc = E.xcount_host + (b * h->N + n) * kXCounts;
+        sa.xs[n + 1] = sa.xs[n] + xc[0];
+        sa.xl[n + 1] = sa.xl[n] + xc[1];
+        sa.xp[n + 1] = sa.xp[n] + xc[2];
+        nmulti += xc[3];
     }
     sa.small_blocks = (sa.xs[h->N] + kSegWaves - 1) / kSegWaves;
-    sa.large_blocks = sa.xl[h->N];
+    sa.large_blocks = sa.xp[h->N];
+    sa.combine_blocks =
+        nmulti > 0 ? (sa.xl[h->N] + kSegWaves - 1) / kSegWaves : 0;
     sa.lr = (float)h->opt.lr_A;
     sa.lam = (float)h->opt.lambda_A;
     sa.mean = h->opt.row_scale == FT_ROW_MEAN;
@@ -894,6 +915,10 @@ static ft_status run_minibatch(ft_handle *h, int64_t b, int apply,
     {
         LaunchExt L(h, FT_K_SEG_REDUCE);
         HIPCHK(h, launch_seg_reduce(sa, h->stream));
+    }
+    if (sa.combine_blocks > 0) {
+        LaunchExt L(h, FT_K_SEG_COMBINE);
+        HIPCHK(h, launch_seg_combine(sa, h->stream));
     }
     return FT_OK;
 }
@@ -903,6 +928,8 @@ static ft_status alloc_factor(ft_handle *h, int64_t nmb, int nper) {
     const int64_t nch = (M + kSegChunk - 1) / kSegChunk;
     (void)nch;
     HIPCHK(h, ensure(&h->G, &h->G_cap, (size_t)h->N * M * h->sh.J4));
+    HIPCHK(h, ensure(&h->P, &h->P_cap,
+                     (size_t)h->N * part_capacity(M) * h->sh.J4));
     HIPCHK(h, ensure(&h->mb_part, &h->mb_part_cap, (size_t)nmb * nper));
     HIPCHK(h, ensure(&h->mb_loss, &h->mb_loss_cap, (size_t)nmb));
     return FT_OK;
@@ -1355,9 +1382,10 @@ extern "C" ft_status ft_profile_get(ft_handle *h, int32_t kernel,
 // ------------------------------------------------------------------ stateless
 namespace {
 struct MbLayout {
-    size_t bpad, G, sk0, sk1, sv0, sv1, inv, counts, xlist, xcount, ordinal,
+    size_t bpad, G, P, sk0, sk1, sv0, sv1, inv, counts, xlist, plist, xcount,
+        ordinal,
         tile_count, total, core_part, dpart, bytes;
-    int xcap;
+    int xcap, pcap;
     int tps, nch, ntiles_scan, nb_core, nb_fact, nb_eval;
     Shape sh;
 };
@@ -1413,7 +1441,10 @@ MbLayout mb_layout(const ft_problem_desc *p, int64_t m) {
     L.counts = take(sizeof(uint32_t) * N * kRadix * L.tps);
     L.xcap = cross_capacity(m);
     L.xlist = take(sizeof(int4) * N * L.xcap);
-    L.xcount = take(sizeof(int32_t) * N * 2);
+    L.pcap = part_capacity(m);
+    L.plist = take(sizeof(int4) * N * L.pcap);
+    L.P = take(sizeof(float) * N * L.pcap * J4);
+    L.xcount = take(sizeof(int32_t) * N * kXCounts);
     L.ordinal = take(sizeof(uint32_t) * N * m);
     L.tile_count = take(sizeof(uint32_t) * N * L.ntiles_scan);
     L.total = take(sizeof(int64_t) * N);
@@ -1601,15 +1632,24 @@ extern "C" ft_status ft_mb_backward(
         cx.xcap = L.xcap;
         for (int n = 0; n < N; ++n) cx.rows[n] = sk[cur] + (size_t)n * m;
         cx.xlist = at<int4>(workspace, L.xlist);
+        cx.plist = at<int4>(workspace, L.plist);
+        cx.pcap = L.pcap;
         cx.xcount = at<int32_t>(workspace, L.xcount);
         HIPCHK0(launch_crossing_segments(cx, s));
         sa.xcount = cx.xcount;
         sa.xcap = L.xcap;
-        // worst case (surplus blocks exit): every crossing row short, and
-        // as many long rows as fit in m
+        // worst case (surplus blocks exit): every crossing row short, every
+        // part slot used, every long row in several parts
+        sa.pcap = L.pcap;
+        sa.P = at<float>(workspace, L.P);
         sa.small_blocks = (N * L.xcap + kSegWaves - 1) / kSegWaves;
-        sa.large_blocks = N * (int)(m / (kSmallCross + 1));
-        for (int n = 0; n < N; ++n) sa.xlist[n] = cx.xlist + (size_t)n * L.xcap;
+        sa.large_blocks = N * L.pcap;
+        sa.combine_blocks = (N * (int)(m / (kSmallCross + 1)) + kSegWaves - 1) /
+                            kSegWaves;
+        for (int n = 0; n < N; ++n) {
+            sa.xlist[n] = cx.xlist + (size_t)n * L.xcap;
+            sa.plist[n] = cx.plist + (size_t)n * L.pcap;
+        }
     }
     for (int n = 0; n < N; ++n) {
         sa.rows[n] = sk[cur] + (size_t)n * m;
@@ -1635,6 +1675,7 @@ extern "C" ft_status ft_mb_backward(
         HIPCHK0(launch_unique_scan(u, s));
     }
     HIPCHK0(launch_seg_reduce(sa, s));
+    HIPCHK0(launch_seg_combine(sa, s));
 
     // core gradients over the minibatch
     CoreArgs ca{};

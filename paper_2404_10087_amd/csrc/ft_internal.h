@@ -38,6 +38,10 @@ constexpr int kSegChunk = 64;
 constexpr int kSmallCross = 256;      // crossing rows up to this many samples
                                       // are reduced by one wave
 constexpr int kSegWaves = 4;          // waves per row-reduction block
+constexpr int kSplitRows = 16384;     // crossing rows of more samples are
+constexpr int kPartRows = 2048;       // summed in parts of kPartRows
+constexpr int kXCounts = 4;           // per minibatch and mode: short rows,
+                                      // long rows, parts, multi-part rows
 
 // Mode-sorted minibatch builder: LSD radix sort, 8-bit digits, 2048-element
 // tiles aligned to minibatch starts.
@@ -142,20 +146,29 @@ struct SegArgs {
     const uint32_t *rows[kMaxOrder];  // sorted rows of the minibatch
     const float *G;                   // [N][m][J4], sorted order per mode
     float *A[kMaxOrder];
-    // rows whose samples cross a chunk edge, entries (first, end, row, -)
-    // in sorted indices. For mode n, xcount[2n] rows of at most kSmallCross
-    // samples fill xlist[n][0..) and xcount[2n+1] longer rows fill
-    // xlist[n][xcap-1..] downwards.
+    // rows whose samples cross a chunk edge, in sorted indices. For mode n,
+    // xcount[kXCounts n] rows of at most kSmallCross samples fill
+    // xlist[n][0..) as (first, end, row, 0) and xcount[kXCounts n + 1]
+    // longer rows fill xlist[n][xcap-1..] downwards as (first, end, row,
+    // first part). A long row is summed in one part, or in
+    // ceil(count / kPartRows) parts when count > kSplitRows;
+    // plist[n][0 .. xcount[kXCounts n + 2]) = (first, end, row, parts of
+    // the row); rows of one part are finished at once, the others leave
+    // partial sums in P[n][part][J4] for the combine kernel.
     const int4 *xlist[kMaxOrder];
+    const int4 *plist[kMaxOrder];
     const int32_t *xcount;
     int xcap;
+    int pcap;
+    float *P;
     // host_counts: the counts are also given here as prefix sums over the
-    // modes (xs: short rows, xl: long rows), so blocks find their entry
-    // without reading xcount
+    // modes (xs: short rows, xl: long rows, xp: parts), so blocks find their
+    // entry without reading xcount
     int host_counts;
-    int xs[kMaxOrder + 1], xl[kMaxOrder + 1];
-    int small_blocks;                 // blocks for the short rows (16 each)
-    int large_blocks;                 // blocks for the long rows (one each)
+    int xs[kMaxOrder + 1], xl[kMaxOrder + 1], xp[kMaxOrder + 1];
+    int small_blocks;                 // blocks for the short rows
+    int large_blocks;                 // blocks for the long-row parts
+    int combine_blocks;               // blocks of the combine kernel (0: none)
     float lr, lam;
     int mean;                         // FT_ROW_MEAN
     int apply;                        // 1: update A; 0: write grad/count;
@@ -174,6 +187,8 @@ struct SegArgs {
     const float *scale;
 };
 hipError_t launch_seg_reduce(const SegArgs &a, hipStream_t s);
+// finishes the long rows of more than one part (a.combine_blocks > 0)
+hipError_t launch_seg_combine(const SegArgs &a, hipStream_t s);
 
 // Per epoch (after the sort): list every row segment of every minibatch
 // and mode that crosses a kSegChunk edge.
@@ -185,13 +200,19 @@ struct CrossArgs {
     int xcap;                         // max(1, ceil(min(M, nnz) / kSegChunk) - 1)
     const uint32_t *rows[kMaxOrder];  // sorted rows of the whole epoch
     int4 *xlist;                      // [nseg][N][xcap]
-    int32_t *xcount;                  // [nseg][N][2] (short, long rows)
+    int4 *plist;                      // [nseg][N][pcap]
+    int pcap;
+    int32_t *xcount;                  // [nseg][N][kXCounts]
     int grid_cap;                     // > 0: at most this many workgroups
 };
 hipError_t launch_crossing_segments(const CrossArgs &c, hipStream_t s);
 inline int cross_capacity(int64_t m) {
     const int64_t ch = (m + kSegChunk - 1) / kSegChunk;
     return ch > 1 ? (int)(ch - 1) : 1;
+}
+// sum over the long rows of ceil(count / kPartRows) <= rows + m / kPartRows
+inline int part_capacity(int64_t m) {
+    return cross_capacity(m) + (int)(m / kPartRows) + 1;
 }
 
 hipError_t launch_sum_blocks(const double *part, int nper, int ngroups,

@@ -447,25 +447,28 @@ __global__ __launch_bounds__(kSortThreads) void sort_downsweep_kernel(
 // (k = 1 .. xcap, in rounds of kCrossThreads edges). A thread whose edge is
 // the first one its row crosses (the row occupies q - 1 and q but not
 // q - kSegChunk - 1) finds the row's first sample in the chunk before q and
-// its end by a galloping search, and lists (first, end, row). Rows of at most kSmallCross samples are
-// listed from the front of the minibatch's list, longer ones from the back,
-// each class in edge order: slots come from a block scan of the flags (wave
-// ballots, then wave totals in LDS), so no atomics and the list is the same
-// on every run.
+// its end by a galloping search, and lists (first, end, row). Rows of at
+// most kSmallCross samples are listed from the front of the minibatch's
+// list, longer ones from the back together with their first part, and every
+// long row is cut into parts of kPartRows samples listed in plist. Each
+// class is in edge order: slots and part offsets come from block scans
+// (wave ballots and shuffle scans, then wave totals in LDS), so no atomics
+// and the lists are the same on every run.
 constexpr int kCrossThreads = 1024;
 
 __device__ __forceinline__ void crossing_one(const CrossArgs &c, int b,
                                              int n) {
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     constexpr int W = kCrossThreads / 64;
-    __shared__ int wtot[2][W];
+    __shared__ int wtot[4][W];
     const int64_t off = (int64_t)b * c.M;
     const int64_t rem = c.nnz - off;
     const int m = (int)(rem < c.M ? rem : c.M);
     const uint32_t *r = c.rows[n] + off;
     int4 *list = c.xlist + ((int64_t)b * c.N + n) * c.xcap;
+    int4 *plist = c.plist + ((int64_t)b * c.N + n) * c.pcap;
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    int nsmall = 0, nlarge = 0;
+    int nsmall = 0, nlarge = 0, nparts = 0, nmulti = 0;
     for (int k0 = 1; k0 <= c.xcap; k0 += kCrossThreads) {
         const int k = k0 + t;
         const int q = k * kSegChunk;
@@ -499,29 +502,58 @@ __device__ __forceinline__ void crossing_one(const CrossArgs &c, int b,
         }
         const bool small = flag && end - first <= kSmallCross;
         const bool large = flag && !small;
+        const int cnt = end - first;
+        const int parts = !large ? 0
+                          : (cnt > kSplitRows ? (cnt + kPartRows - 1) / kPartRows
+                                              : 1);
+        // inclusive scan of the part counts over the wave
+        int pincl = parts;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int y = __shfl_up(pincl, d);
+            if (lane >= d) pincl += y;
+        }
         const uint64_t bs = __ballot(small), bl = __ballot(large);
+        const uint64_t bm = __ballot(parts > 1);
+        if (lane == 63) wtot[2][w] = pincl;
         if (lane == 0) {
             wtot[0][w] = __popcll(bs);
             wtot[1][w] = __popcll(bl);
+            wtot[3][w] = __popcll(bm);
         }
         __syncthreads();
-        int ps = nsmall, pl = nlarge;
+        int ps = nsmall, pl = nlarge, pp = nparts;
         for (int v = 0; v < w; ++v) {
             ps += wtot[0][v];
             pl += wtot[1][v];
+            pp += wtot[2][v];
         }
-        const int4 e = make_int4(first, end, (int)row, 0);
-        if (small) list[ps + __popcll(bs & lt)] = e;
-        if (large) list[c.xcap - 1 - (pl + __popcll(bl & lt))] = e;
+        if (small) list[ps + __popcll(bs & lt)] = make_int4(first, end, (int)row, 0);
+        if (large) {
+            const int p0 = pp + pincl - parts;
+            list[c.xcap - 1 - (pl + __popcll(bl & lt))] =
+                make_int4(first, end, (int)row, p0);
+            const int span = parts == 1 ? cnt : kPartRows;   // whole row
+            for (int j = 0; j < parts; ++j) {
+                const int f = first + j * span;
+                const int e = f + span < end ? f + span : end;
+                plist[p0 + j] = make_int4(f, e, (int)row, parts);
+            }
+        }
         for (int v = 0; v < W; ++v) {
             nsmall += wtot[0][v];
             nlarge += wtot[1][v];
+            nparts += wtot[2][v];
+            nmulti += wtot[3][v];
         }
         __syncthreads();
     }
     if (t == 0) {
-        c.xcount[(b * c.N + n) * 2] = nsmall;
-        c.xcount[(b * c.N + n) * 2 + 1] = nlarge;
+        int32_t *xc = c.xcount + (int64_t)(b * c.N + n) * kXCounts;
+        xc[0] = nsmall;
+        xc[1] = nlarge;
+        xc[2] = nparts;
+        xc[3] = nmulti;
     }
 }
 

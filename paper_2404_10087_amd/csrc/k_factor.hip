@@ -438,7 +438,9 @@ __device__ __forceinline__ void finish_row(const SegArgs &a, int n,
 // One launch, three kinds of blocks (kSegWaves waves each), longest work
 // first so that it starts at once:
 //  * long crossing rows (blocks [0, large_blocks)): one block per row of
-//    more than kSmallCross samples, from the back of the builder's list;
+//    more than kSmallCross samples, or, for a row of more than kSplitRows,
+//    one block per part of kPartRows samples; a row of one part is finished
+//    at once, the others leave part sums for seg_combine_kernel;
 //  * chunks (the next chunk_blocks): one wave per chunk of 64 sorted
 //    samples of one mode; lane l holds sample i0 + l with its whole gradient
 //    row. A segmented inclusive scan across the lanes (Hillis-Steele, steps
@@ -456,7 +458,7 @@ __device__ __forceinline__ void finish_row(const SegArgs &a, int n,
 constexpr int kSegThreads = 64 * kSegWaves;
 
 // rows loaded per thread before they are added
-constexpr int seg_unroll(int J4) { return J4 <= 16 ? 4 : (J4 <= 20 ? 2 : 1); }
+constexpr int seg_unroll(int J4) { return J4 <= 16 ? 4 : 2; }
 
 // Sum of the gradient rows [se.x, se.y) of mode n (contiguous in the sorted
 // order), thread t of a group of `stride` taking rows t, t + stride, ...,
@@ -492,20 +494,34 @@ __device__ __forceinline__ void sum_rows_strided(const SegArgs &a, int n,
         for (int q = 0; q < J4; ++q) acc[q] += __shfl_xor(acc[q], d);
 }
 
-// Entry k of one size class (cls 0: short, 1: long) over the modes in order:
-// returns the mode (N if k is past the last entry) and leaves the index
-// within that mode's class in k.
+// Entry k of one class (cls 0: short rows, 1: long rows, 2: long-row
+// parts) over the modes in order: returns the mode (N if k is past the last
+// entry) and leaves the index within that mode's class in k.
 __device__ __forceinline__ int find_mode(const SegArgs &a, int cls, int &k) {
     if (a.host_counts) {
-        const int *pre = cls ? a.xl : a.xs;
+        const int *pre = cls == 0 ? a.xs : (cls == 1 ? a.xl : a.xp);
         int n = 0;
         while (n < a.N && k >= pre[n + 1]) ++n;
         if (n < a.N) k -= pre[n];
         return n;
     }
     int n = 0;
-    while (n < a.N && k >= a.xcount[2 * n + cls]) k -= a.xcount[2 * n++ + cls];
+    while (n < a.N && k >= a.xcount[kXCounts * n + cls])
+        k -= a.xcount[kXCounts * n++ + cls];
     return n;
+}
+
+// Fixed-order sum of the block's wave sums (in red[w][0..J4)): lane q < J4
+// of wave 0 returns entry q, and g of every lane gets the whole row.
+template <int J4>
+__device__ __forceinline__ float sum_waves(float (*red)[J4 + 1], int lane,
+                                           float (&g)[J4]) {
+    float v = 0.f;
+    if (lane < J4)
+        for (int ww = 0; ww < kSegWaves; ++ww) v += red[ww][lane];
+#pragma unroll
+    for (int q = 0; q < J4; ++q) g[q] = __shfl(v, q);
+    return v;
 }
 
 template <int KQ>
@@ -516,25 +532,24 @@ __global__ __launch_bounds__(kSegThreads) void seg_reduce_kernel(
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     int j = blockIdx.x;
     if (j < a.large_blocks) {
-        const int n = find_mode(a, 1, j);          // long row j (block-uniform)
+        const int n = find_mode(a, 2, j);     // long-row part j (block-uniform)
         if (n == a.N) return;
-        const int4 se = a.xlist[n][a.xcap - 1 - j];
+        const int4 pt = a.plist[n][j];        // (first, end, row, parts)
         float acc[J4];
-        sum_rows_strided<J4>(a, n, se, t, kSegThreads, acc);
+        sum_rows_strided<J4>(a, n, pt, t, kSegThreads, acc);
         if (lane == 0)
 #pragma unroll
             for (int q = 0; q < J4; ++q) red[w][q] = acc[q];
         __syncthreads();
         if (w == 0) {
-            // lane q < J4 adds entry q of the wave sums in order
-            float v = 0.f;
-            if (lane < J4)
-                for (int ww = 0; ww < kSegWaves; ++ww) v += red[ww][lane];
             float g[J4];
-#pragma unroll
-            for (int q = 0; q < J4; ++q) g[q] = __shfl(v, q);
-            if (lane == 0)
-                finish_row<J4>(a, n, (uint32_t)se.z, g, se.y - se.x, se.x);
+            const float v = sum_waves<J4>(red, lane, g);
+            if (pt.w == 1) {                  // the whole row: finish it
+                if (lane == 0)
+                    finish_row<J4>(a, n, (uint32_t)pt.z, g, pt.y - pt.x, pt.x);
+            } else if (lane < J4) {           // one part: leave its sum
+                a.P[((int64_t)n * a.pcap + j) * J4 + lane] = v;
+            }
         }
         return;
     }
@@ -602,6 +617,59 @@ static hipError_t launch_seg_kq(const SegArgs &a, hipStream_t s) {
     FT_LAUNCH(seg_reduce_kernel<KQ>, dim3(blocks), dim3(kSegThreads), 0, s, a,
               chunk_blocks);
     return hipGetLastError();
+}
+
+// Long rows of more than one part: one wave per long row (rows of one part
+// were finished by the reduction kernel and are skipped); lane l adds the
+// row's part sums l, l + 64, ... and a fixed butterfly adds the lanes.
+template <int KQ>
+__global__ __launch_bounds__(kSegThreads) void seg_combine_kernel(SegArgs a) {
+    constexpr int J4 = 4 * KQ;
+    const int lane = threadIdx.x & 63;
+    int k = blockIdx.x * kSegWaves + (threadIdx.x >> 6);
+    const int n = find_mode(a, 1, k);
+    if (n == a.N) return;                            // wave-uniform
+    const int4 e = a.xlist[n][a.xcap - 1 - k];       // (first, end, row, p0)
+    const int cnt = e.y - e.x;
+    if (cnt <= kSplitRows) return;                   // finished in one part
+    const int parts = (cnt + kPartRows - 1) / kPartRows;
+    float acc[J4];
+#pragma unroll
+    for (int q = 0; q < J4; ++q) acc[q] = 0.f;
+    const float *P = a.P + ((int64_t)n * a.pcap + e.w) * J4;
+    for (int i = lane; i < parts; i += 64) {
+        float g[J4];
+        load_row_part<J4>(P + (int64_t)i * J4, g);
+#pragma unroll
+        for (int q = 0; q < J4; ++q) acc[q] += g[q];
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1)
+#pragma unroll
+        for (int q = 0; q < J4; ++q) acc[q] += __shfl_xor(acc[q], d);
+    if (lane == 0) finish_row<J4>(a, n, (uint32_t)e.z, acc, e.y - e.x, e.x);
+}
+
+template <int KQ>
+static hipError_t launch_comb_kq(const SegArgs &a, hipStream_t s) {
+    FT_LAUNCH(seg_combine_kernel<KQ>, dim3(a.combine_blocks), dim3(kSegThreads),
+              0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_seg_combine(const SegArgs &a, hipStream_t s) {
+    if (a.combine_blocks <= 0) return hipSuccess;
+    switch (a.J4) {
+    case 4: return launch_comb_kq<1>(a, s);
+    case 8: return launch_comb_kq<2>(a, s);
+    case 12: return launch_comb_kq<3>(a, s);
+    case 16: return launch_comb_kq<4>(a, s);
+    case 20: return launch_comb_kq<5>(a, s);
+    case 24: return launch_comb_kq<6>(a, s);
+    case 28: return launch_comb_kq<7>(a, s);
+    case 32: return launch_comb_kq<8>(a, s);
+    }
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_seg_reduce(const SegArgs &a, hipStream_t s) {

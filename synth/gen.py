@@ -97,10 +97,10 @@ class _Zipf:
         return self.label[k]
 
 
-def zipf_distinct(seed, dims, s, count):
+def zipf_distinct(seed, dims, s, count, progress=None):
     """count distinct coordinates with every mode's index drawn Zipf(s); the
     tuples are deduplicated and redrawn until enough are distinct, kept in
-    first-drawn order."""
+    first-drawn order. progress(msg), if given, hears about every round."""
     rng = _rng(seed)
     dims = [int(d) for d in dims]
     samplers = [_Zipf(rng, d, s) for d in dims]
@@ -117,13 +117,16 @@ def zipf_distinct(seed, dims, s, count):
         gained = max(idx.shape[1] - have, 1)
         ratio = min(64.0, 1.1 * m / gained)
         rounds += 1
+        if progress:
+            progress(f"zipf round {rounds}: {min(idx.shape[1], count)} of "
+                     f"{count} distinct")
         if rounds > 200:
             raise RuntimeError("cannot draw enough distinct coordinates")
     return np.ascontiguousarray(idx[:, :count])
 
 
 def planted_values(seed, dims, idx, J, R, a_std, b_std, scale=1.0,
-                   chunk=1 << 20):
+                   chunk=1 << 20, progress=None):
     """Values of a planted low-rank tensor at the coordinates idx.
 
     Data synthesis only: draws planted matrices P^(n) (I_n x J) and
@@ -146,6 +149,8 @@ def planted_values(seed, dims, idx, J, R, a_std, b_std, scale=1.0,
         for n, u in enumerate(U):
             prod *= u[idx[n, lo:hi]]
         out[lo:hi] = prod.sum(axis=1) * scale
+        if progress and (hi // chunk) % 32 == 0:
+            progress(f"planted values {hi} of {nnz}")
     return out
 
 
@@ -163,10 +168,11 @@ class Tensor:
         return len(self.dims)
 
 
-def make_tensor(w, seed=None, cache_dir=None):
+def make_tensor(w, seed=None, cache_dir=None, progress=None):
     """Build the synthetic tensor of a Workload (see configs.py). With
     cache_dir, a tensor generated before for the same workload and seed is
-    loaded from there (a plain .npz, no pickles) instead."""
+    loaded from there (a plain .npz, no pickles) instead. progress(msg), if
+    given, hears about the generation steps."""
     seed = w.data_seed if seed is None else seed
     if cache_dir:
         import hashlib
@@ -179,7 +185,7 @@ def make_tensor(w, seed=None, cache_dir=None):
                           train_val=z["train_val"], test_idx=z["test_idx"],
                           test_val=z["test_val"],
                           meta={"workload": w.name, "seed": seed})
-        T = make_tensor(w, seed)
+        T = make_tensor(w, seed, progress=progress)
         os.makedirs(cache_dir, exist_ok=True)
         tmp = path + ".tmp.npz"
         np.savez(tmp, train_idx=T.train_idx, train_val=T.train_val,
@@ -190,9 +196,10 @@ def make_tensor(w, seed=None, cache_dir=None):
     if w.index_dist == "uniform":
         idx = uniform_distinct(rng, w.dims, w.nnz)
     else:
-        idx = zipf_distinct(rng, w.dims, w.zipf_s, w.nnz)
+        idx = zipf_distinct(rng, w.dims, w.zipf_s, w.nnz, progress=progress)
     x = planted_values(rng, w.dims, idx, w.planted_rank, w.planted_rank,
-                       w.planted_a_std, w.planted_b_std, w.planted_scale)
+                       w.planted_a_std, w.planted_b_std, w.planted_scale,
+                       progress=progress)
     x = x + rng.normal(0.0, w.noise_std, size=x.shape)
     if w.values == "rating":
         x = np.clip(np.rint(w.rating_offset + x), 1.0, 5.0)

@@ -64,7 +64,10 @@ def test_backward_matches_fp64_finite_differences():
 
 @pytest.mark.parametrize("J,R,dims,m", [(4, 4, (100, 100, 100), 9000),
                                         (16, 16, (300, 200, 50), 20000),
-                                        (3, 5, (40, 30, 20, 10), 3000)])
+                                        (3, 5, (40, 30, 20, 10), 3000),
+                                        # rows of ~30,000 samples, summed
+                                        # in several parts
+                                        (8, 16, (2000, 1500, 4), 70000)])
 def test_backward_matches_oracle_gradients_dense_and_sparse(J, R, dims, m):
     w = synth.get("c0", dims=dims, nnz=int(m / 0.9) + 1, J=J, R=R,
                   index_dist="zipf", zipf_s=1.1)

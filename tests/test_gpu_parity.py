@@ -45,6 +45,11 @@ W = {
     "M1": synth.get("c0", name="m1", dims=(5, 6, 7), nnz=60, J=4, R=4, M=1),
     "nnz_lt_M": synth.get("c0", name="small", dims=(20, 20, 20), nnz=120,
                           J=4, R=4, M=512),
+    # rows of ~20,000-30,000 samples per minibatch: long crossing rows
+    # summed in several parts and combined
+    "hot": synth.get("c0", name="hot", dims=(2000, 1500, 4), nnz=250_000,
+                     J=8, R=16, M=65536, index_dist="zipf", zipf_s=1.1,
+                     row_mean=True, init_a_std=0.3, init_b_std=0.3),
 }
 
 
@@ -132,7 +137,8 @@ def test_factor_minibatch_gradients(name):
 
 @pytest.mark.parametrize("name,row_mean", [("c0", False), ("c0", True),
                                            ("zipf", True), ("order4", False),
-                                           ("pad_J3_R5", True)])
+                                           ("pad_J3_R5", True), ("hot", True),
+                                           ("hot", False)])
 def test_factor_minibatch_update(name, row_mean):
     w = W[name]
     ft, T, A0, B0 = setup(w, with_test=False)

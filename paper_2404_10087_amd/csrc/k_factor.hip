@@ -46,18 +46,32 @@ struct FactorTile {
     static constexpr int J4 = 4 * KQ;
     static constexpr int R16 = 16 * RB;
     static constexpr int JB = (KQ + 3) / 4;   // 16-row output blocks of J4
-    int q, c;
-    // A-operands: B^(n)T for the contraction over j (FP32, BF16 or FP8
-    // packs),
-    // B^(n) for the one over r (FP32)
+    // Operand words per lane: the A-operands B^(n)T of the contraction over
+    // j (FP32, BF16 or FP8 packs) and B^(n) of the one over r (FP32). They
+    // are the same in every wave; small sets stay in registers, large ones
+    // (J = R = 32 and order 4-5: up to 160 words) are kept in LDS, one copy
+    // per block laid out [word][lane], and read when a step needs them, so
+    // the registers go to waves in flight instead.
+    static constexpr int CFW = sizeof(ColFrag<KQ, P>) / 4;
+    static constexpr int OPW = N * RB * CFW + N * JB * RB * 4;
+    static constexpr bool kLdsOps = OPW > 48;
+    int q, c, lane;
     ColFrag<KQ, P> bf[N][RB];
     float bb[N][JB][RB][4];
+    const uint32_t *ops;             // LDS operand words (kLdsOps)
     floatx4 D[N][RB];
 
-    __device__ __forceinline__ void load_B(const float *const *Bm) {
-        const int lane = threadIdx.x & 63;
+    // Operands from the (LDS-staged) B. With kLdsOps wave 0 writes them to
+    // ops_lds and the caller synchronises the block before the first tile.
+    __device__ __forceinline__ void load_B(const float *const *Bm,
+                                           uint32_t *ops_lds) {
+        lane = threadIdx.x & 63;
         q = lane >> 4;
         c = lane & 15;
+        ops = ops_lds;
+        if constexpr (kLdsOps) {
+            if (threadIdx.x >= 64) return;
+        }
 #pragma unroll
         for (int n = 0; n < N; ++n) {
             const float *B = Bm[n];
@@ -74,6 +88,62 @@ struct FactorTile {
                             j < J4 ? B[j * R16 + 16 * rb + 4 * q + v] : 0.f;
             }
         }
+        if constexpr (kLdsOps) {
+#pragma unroll
+            for (int n = 0; n < N; ++n)
+#pragma unroll
+                for (int rb = 0; rb < RB; ++rb) {
+                    uint32_t w[CFW];
+                    __builtin_memcpy(w, &bf[n][rb], sizeof(w));
+#pragma unroll
+                    for (int i = 0; i < CFW; ++i)
+                        ops_lds[((n * RB + rb) * CFW + i) * 64 + lane] = w[i];
+                }
+#pragma unroll
+            for (int n = 0; n < N; ++n)
+#pragma unroll
+                for (int jb = 0; jb < JB; ++jb)
+#pragma unroll
+                    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                        for (int v = 0; v < 4; ++v)
+                            ops_lds[(N * RB * CFW +
+                                     ((n * JB + jb) * RB + rb) * 4 + v) * 64 +
+                                    lane] = __float_as_uint(bb[n][jb][rb][v]);
+        }
+    }
+
+    // The lane index is passed through an empty asm statement at every use,
+    // so the compiler cannot hoist the LDS reads out of the tile loop (which
+    // would bring the operands back into registers).
+    __device__ __forceinline__ int opaque_lane() const {
+        int l = lane;
+        asm volatile("" : "+v"(l));
+        return l;
+    }
+
+    __device__ __forceinline__ ColFrag<KQ, P> bfrag(int n, int rb) const {
+        if constexpr (kLdsOps) {
+            const uint32_t *o = ops + opaque_lane();
+            uint32_t w[CFW];
+#pragma unroll
+            for (int i = 0; i < CFW; ++i)
+                w[i] = o[((n * RB + rb) * CFW + i) * 64];
+            ColFrag<KQ, P> f;
+            __builtin_memcpy(&f, w, sizeof(w));
+            return f;
+        } else {
+            return bf[n][rb];
+        }
+    }
+
+    __device__ __forceinline__ float bbv(int n, int jb, int rb, int v) const {
+        if constexpr (kLdsOps)
+            return __uint_as_float(
+                ops[(N * RB * CFW + ((n * JB + jb) * RB + rb) * 4 + v) * 64 +
+                    opaque_lane()]);
+        else
+            return bb[n][jb][rb][v];
     }
 
     // Gather the rows of sample ps (this lane's column).
@@ -106,10 +176,10 @@ struct FactorTile {
         for (int n = 0; n < N; ++n)
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb) {
-                C[n][rb] = contract(bf[n][rb], arow[n],
-                                    floatx4{0.f, 0.f, 0.f, 0.f});
+                const ColFrag<KQ, P> x = bfrag(n, rb);
+                C[n][rb] = contract(x, arow[n], floatx4{0.f, 0.f, 0.f, 0.f});
                 if constexpr (P == kFP8)
-                    C[n][rb] = fp8_scale_ct(C[n][rb], bf[n][rb].s, arow[n].s, q);
+                    C[n][rb] = fp8_scale_ct(C[n][rb], x.s, arow[n].s, q);
             }
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb) {
@@ -141,7 +211,7 @@ struct FactorTile {
         for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
             for (int v = 0; v < 4; ++v)
-                acc = mfma_16x16x4(bb[n][jb][rb][v], r * D[n][rb][v], acc);
+                acc = mfma_16x16x4(bbv(n, jb, rb, v), r * D[n][rb][v], acc);
         return acc;
     }
 };
@@ -169,6 +239,7 @@ __global__ __launch_bounds__(kFactorThreads) void factor_grad_kernel(
     FactorArgs a, int ntiles) {
     using T = FactorTile<N, KQ, RB, P>;
     __shared__ float sB[N * T::J4 * T::R16];
+    __shared__ uint32_t sOps[T::kLdsOps ? T::OPW * 64 : 1];
     T tl;
     tl.q = (threadIdx.x & 63) >> 4;
     tl.c = threadIdx.x & 15;
@@ -188,7 +259,8 @@ __global__ __launch_bounds__(kFactorThreads) void factor_grad_kernel(
     }
     const float *sBm[N];
     stage_B<N, T::J4 * T::R16>(a.B, sB, sBm);
-    tl.load_B(sBm);
+    tl.load_B(sBm, sOps);
+    if constexpr (T::kLdsOps) __syncthreads();
     for (; tile < ntiles; tile += nwaves) {
         const int p = tile * 16 + tl.c;
         const bool valid = p < a.m;
@@ -233,10 +305,12 @@ template <int N, int KQ, int RB>
 __global__ __launch_bounds__(kFactorThreads) void hogwild_kernel(HogArgs a) {
     using T = FactorTile<N, KQ, RB, kF32>;
     __shared__ float sB[N * T::J4 * T::R16];
+    __shared__ uint32_t sOps[T::kLdsOps ? T::OPW * 64 : 1];
     const float *sBm[N];
     stage_B<N, T::J4 * T::R16>(a.B, sB, sBm);
     T tl;
-    tl.load_B(sBm);
+    tl.load_B(sBm, sOps);
+    if constexpr (T::kLdsOps) __syncthreads();
     const int64_t ntiles = (a.count + 15) / 16;
     const int64_t nwaves = (int64_t)gridDim.x * (kFactorThreads / 64);
     for (int64_t tile = (int64_t)blockIdx.x * (kFactorThreads / 64) +

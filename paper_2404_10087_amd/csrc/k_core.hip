@@ -65,6 +65,8 @@ __device__ __forceinline__ void load_core_tile(const CoreArgs &a, int64_t tile,
 // in 128 registers without spilling (checked per shape at build time), else
 // the compiler's choice.
 constexpr int core_waves(int N, int KQ, int RB, int P) {
+    if (N * RB * KQ > 32)   // B-operands in LDS: two waves fit, except
+        return (P == kF32 && N == 5 && KQ * RB >= 14) ? 1 : 2;  // (spills)
     if (P == kFP8)   // the scale shuffles need a few more registers
         return (KQ * RB <= 4 && RB == 1 && (N <= 3 || (N == 4 && KQ <= 2)))
                    ? 4
@@ -92,12 +94,46 @@ core_grad_kernel(CoreArgs a, int64_t ntiles) {
                                                           : N * 16 * TP;
     float *tr = lds + wave * WAVE_LDS;
 
-    ColFrag<KQ, P> bop[N][RB];   // B-operand: B[k = KQ*q + t][r = 16 rb + c]
+    // B-operands B[k = KQ*q + t][r = 16 rb + c]: the same in every wave.
+    // Large sets (order 4-5 at J = R = 32) live in LDS, one copy per block
+    // laid out [word][lane], written by wave 0 and read at each use (the
+    // lane index goes through an empty asm statement so the reads are not
+    // hoisted back into registers); small sets stay in registers.
+    constexpr int CFW = sizeof(ColFrag<KQ, P>) / 4;
+    constexpr bool kLdsOps = N * RB * CFW > 32;
+    __shared__ uint32_t sOps[kLdsOps ? N * RB * CFW * 64 : 1];
+    ColFrag<KQ, P> bop[N][RB];
+    if (!kLdsOps || wave == 0) {
 #pragma unroll
-    for (int n = 0; n < N; ++n)
+        for (int n = 0; n < N; ++n)
 #pragma unroll
-        for (int rb = 0; rb < RB; ++rb)
-            bop[n][rb].load(a.B[n], R16, q, 16 * rb + c);
+            for (int rb = 0; rb < RB; ++rb) {
+                bop[n][rb].load(a.B[n], R16, q, 16 * rb + c);
+                if constexpr (kLdsOps) {
+                    uint32_t w[CFW];
+                    __builtin_memcpy(w, &bop[n][rb], sizeof(w));
+#pragma unroll
+                    for (int i = 0; i < CFW; ++i)
+                        sOps[((n * RB + rb) * CFW + i) * 64 + lane] = w[i];
+                }
+            }
+    }
+    if constexpr (kLdsOps) __syncthreads();
+    auto operand = [&](int n, int rb) -> ColFrag<KQ, P> {
+        if constexpr (kLdsOps) {
+            int l = lane;
+            asm volatile("" : "+v"(l));
+            uint32_t w[CFW];
+#pragma unroll
+            for (int i = 0; i < CFW; ++i)
+                w[i] = sOps[((n * RB + rb) * CFW + i) * 64 + l];
+            ColFrag<KQ, P> f;
+            __builtin_memcpy(&f, w, sizeof(w));
+            return f;
+        } else {
+            return bop[n][rb];
+        }
+    };
 
     floatx4 grad[N][JB][RB];
 #pragma unroll
@@ -125,10 +161,11 @@ core_grad_kernel(CoreArgs a, int64_t ntiles) {
         for (int n = 0; n < N; ++n)
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb) {
-                C[n][rb] = contract(cur.arow[n], bop[n][rb],
+                const ColFrag<KQ, P> bo = operand(n, rb);
+                C[n][rb] = contract(cur.arow[n], bo,
                                     floatx4{0.f, 0.f, 0.f, 0.f});
                 if constexpr (P == kFP8)
-                    C[n][rb] = fp8_scale_c(C[n][rb], bop[n][rb].s,
+                    C[n][rb] = fp8_scale_c(C[n][rb], bo.s,
                                            cur.arow[n].s, q);
             }
         floatx4 D[N][RB];

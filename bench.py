@@ -262,6 +262,10 @@ def main():
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic,
                      "alg_bytes_per_launch": alg_bytes,
+                     "timing": "HIP events on the library stream over "
+                               f"{args.profile_steps} epochs after the timed "
+                               "ones (events inside the timed epochs slow "
+                               "them)",
                      "avg_launch_us": avg_s * 1e6},
         "cpu_baseline": cpu,
         "phase_ms_per_epoch": {"factor": 1000 * t_factor / args.steps,

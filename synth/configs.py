@@ -102,6 +102,24 @@ CONFIGS = {
 }
 
 
+# Order and rank sweep in the manner of the paper's scaling study (Fig. 2,
+# Table 10): I_n = 10,000 in every mode, J = R in {16, 32}, orders 3..5
+# (the device path covers N <= 5), ratings 1..5 from a planted model, uniform
+# indices; 10M nonzeros (the paper's 1e8 scaled down tenfold), M = 65,536.
+for _n in (3, 4, 5):
+    for _r in (16, 32):
+        CONFIGS[f"sweep-N{_n}-R{_r}"] = Workload(
+            name=f"sweep-order{_n}-1e4^{_n}-10M-uniform-rating-J{_r}R{_r}",
+            dims=(10_000,) * _n, nnz=10_000_000, J=_r, R=_r, M=65_536,
+            epochs=5, lr_A=0.01, lr_B=0.1, lam_A=1e-3, lam_B=1e-3,
+            row_mean=True, index_dist="uniform", values="rating",
+            rating_offset=3.0, noise_std=0.3, planted_rank=_r,
+            planted_a_std=1.0, planted_b_std=_r ** -0.5,
+            planted_scale=_r ** -0.5, init_dist="normal",
+            init_a_std=0.3, init_b_std=0.3, data_seed=1100 + 10 * _n + _r,
+            init_seed=2100 + 10 * _n + _r, order_seed=3100 + 10 * _n + _r)
+
+
 def get(key, **overrides):
     w = CONFIGS[key]
     return replace(w, **overrides) if overrides else w

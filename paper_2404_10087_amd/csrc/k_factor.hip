@@ -647,17 +647,11 @@ __global__ __launch_bounds__(kSegThreads) void seg_reduce_kernel(
     const bool valid = i < i1;
     const uint32_t *rows = a.rows[n];
     const uint32_t row = valid ? rows[i] : 0xffffffffu;
-    float g[J4];
-    if (valid) {
-        load_row_part<J4>(a.G + ((int64_t)n * a.m + i) * J4, g);
-    } else {
-#pragma unroll
-        for (int q = 0; q < J4; ++q) g[q] = 0.f;
-    }
     const uint32_t before_chunk = i0 > 0 ? rows[i0 - 1] : 0xffffffffu;
     const uint32_t after_chunk = i1 < a.m ? rows[i1] : 0xffffffffu;
     const uint32_t below = __shfl_up(row, 1);
     const uint32_t above = __shfl_down(row, 1);
+    const uint32_t last_row = __shfl(row, i1 - 1 - i0);
     const bool head = lane == 0 || row != below;
     int s = head ? lane : 0;                      // first lane of my segment
 #pragma unroll
@@ -667,9 +661,19 @@ __global__ __launch_bounds__(kSegThreads) void seg_reduce_kernel(
     }
     const bool last_in_chunk = i == i1 - 1;
     const bool tail = valid && (last_in_chunk || above != row);
-    const bool crosses = (s == 0 && before_chunk == row) ||
-                         (last_in_chunk && after_chunk == row);
-    const bool finish = tail && !crosses;
+    // the chunk's first segment may continue from the previous chunk and
+    // its last one into the next: such rows are finished by their own
+    // waves, so their gradient rows are not loaded here
+    const bool in_crossing = (s == 0 && before_chunk == row) ||
+                             (row == last_row && after_chunk == row);
+    const bool finish = tail && !in_crossing;
+    float g[J4];
+    if (valid && !in_crossing) {
+        load_row_part<J4>(a.G + ((int64_t)n * a.m + i) * J4, g);
+    } else {
+#pragma unroll
+        for (int q = 0; q < J4; ++q) g[q] = 0.f;
+    }
     float av[J4];
     if (finish) load_av<J4>(a, n, row, av);
 #pragma unroll

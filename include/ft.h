@@ -149,8 +149,13 @@ ft_status ft_num_minibatches(const ft_handle *h, int64_t *out);
  * residual and the row gradients (Eq. (8)) with all parameters as they stand
  * at the minibatch start, and update every touched row (Eq. (12), scaled by
  * row_scale). mb_loss (NULL or [ceil(nnz/M)]) receives sum r^2/2 of every
- * minibatch, r = xhat - x. Advances the epoch counter. In the fast mode the
- * tiles run concurrently with immediate per-sample steps
+ * minibatch, r = xhat - x. Advances the epoch counter. Returns after the
+ * epoch's work is complete. With the device-side order and
+ * reshuffle_each_epoch = 1 the order, permutation and sort of the NEXT epoch
+ * are built on an internal second stream (non-blocking, default priority)
+ * while this epoch's minibatches run; the next call uses them if the
+ * options, seed and training set are unchanged, else rebuilds in line. In
+ * the fast mode the tiles run concurrently with immediate per-sample steps
  * a <- a - lr_A (r B d + lambda_A a) (Eq. (12) applied per sample, Hogwild);
  * row_scale does not apply. */
 ft_status ft_epoch_factors(ft_handle *h, double *mb_loss);
@@ -193,10 +198,10 @@ ft_status ft_get_params(ft_handle *h, int mode, int which, float *host_out);
 ft_status ft_set_params(ft_handle *h, int mode, int which,
                         const float *host_in);
 
-/* Builder output of the prepared epoch, for verification: the epoch order
- * (nnz_train entries), and for minibatch b and mode n the in-minibatch
- * positions sorted stably by row (pos[m]) and those rows (rows[m]),
- * m = size of minibatch b. */
+/* Builder output of the current epoch (after ft_prepare_epoch or
+ * ft_epoch_factors), for verification: the epoch order (nnz_train entries),
+ * and for minibatch b and mode n the in-minibatch positions sorted stably by
+ * row (pos[m]) and those rows (rows[m]), m = size of minibatch b. */
 ft_status ft_get_epoch_order(ft_handle *h, int64_t *perm_out);
 ft_status ft_get_minibatch_sort(ft_handle *h, int64_t b, int mode,
                                 int32_t *pos, int32_t *rows);

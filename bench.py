@@ -111,7 +111,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=46 * 65536)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-low-precision", action="store_true",
-                    help="skip the BF16, FP8 and Hogwild comparison runs")
+                    help="skip the BF16, FP8, Hogwild and vector-ALU "
+                    "comparison runs")
     ap.add_argument("--cache-dir", default=os.environ.get("FT_SYNTH_CACHE"),
                     help="reuse the generated tensor across runs")
     ap.add_argument("--copy-calibration", type=int, default=0,
@@ -213,24 +214,38 @@ def main():
                      "avg_us": round(1000 * v[1] / max(v[0], 1), 3)}
                  for k, v in stats.items()}
 
-    # the same epochs with the low-precision contractions and with the
-    # Hogwild fast mode (same initial parameters and epoch orders), each with
-    # its own test RMSE
+    # the same epochs with the low-precision contractions, with the Hogwild
+    # fast mode and with vector-ALU factor contractions (same initial
+    # parameters and epoch orders), each with its own test RMSE
     low = {}
-    for pname, pcode in (("bf16", 1), ("fp8_e4m3", 2), ("hogwild_fp32", 0)):
+    for pname, pcode in (("bf16", 1), ("fp8_e4m3", 2), ("hogwild_fp32", 0),
+                         ("fp32_vector_alu", 0)):
         if args.no_low_precision:
             break
         del ft
         ft = make(pcode)
-        if pname.startswith("hogwild"):
-            # the paper's execution model: no minibatch barrier, atomic
-            # per-tile row updates (not reproducible; for comparison only)
-            ft.set_options(deterministic=0)
+        try:
+            if pname.startswith("hogwild"):
+                # the paper's execution model: no minibatch barrier, atomic
+                # per-tile row updates (not reproducible; for comparison)
+                ft.set_options(deterministic=0)
+            if pname.endswith("vector_alu"):
+                # matrix-core ablation: factor contractions on vector FMAs
+                ft.set_options(vector_alu=1)
+        except FtError as e:
+            low[pname] = {"error": str(e)}
+            continue
         try:
             el, tf, tc = timed(ft)
-            for _ in range(args.profile_steps):   # same epoch count as FP32
+            ft.profile(True)     # same epoch count as FP32, kernel events on
+            ft.profile_reset()
+            for _ in range(args.profile_steps):
                 ft.epoch_factors()
                 ft.epoch_core()
+            lstats = {k: ft.profile_get(k) for k in
+                      ("factor_grad", "seg_reduce", "hogwild",
+                       "core_grad")}
+            ft.profile(False)
         except FtError as e:     # e.g. a Hogwild run that diverges
             low[pname] = {"error": str(e)}
             continue
@@ -238,7 +253,10 @@ def main():
                       "ms_per_step": 1000.0 * el / args.steps,
                       "factor_nnz_per_s": nnz / (tf / args.steps),
                       "core_nnz_per_s": nnz / (tc / args.steps),
-                      "test_rmse": ft.rmse(FT_TEST)}
+                      "test_rmse": ft.rmse(FT_TEST),
+                      "kernel_avg_us": {
+                          k: round(1000 * v[1] / max(v[0], 1), 3)
+                          for k, v in lstats.items() if v[0]}}
 
     cpu = None
     if not args.no_cpu_baseline:

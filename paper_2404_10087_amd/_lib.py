@@ -26,7 +26,8 @@ class Options(C.Structure):
                 ("lambda_B", C.c_double), ("precision", C.c_int32),
                 ("row_scale", C.c_int32), ("core_step", C.c_int32),
                 ("deterministic", C.c_int32), ("shuffle_seed", C.c_uint64),
-                ("reshuffle_each_epoch", C.c_int32)]
+                ("reshuffle_each_epoch", C.c_int32),
+                ("vector_alu", C.c_int32)]
 
 
 class ProblemDesc(C.Structure):

@@ -338,6 +338,7 @@ extern "C" ft_status ft_default_options(ft_options *o) {
     o->deterministic = 1;
     o->shuffle_seed = 0;
     o->reshuffle_each_epoch = 1;
+    o->vector_alu = 0;
     return FT_OK;
 }
 
@@ -378,6 +379,15 @@ static ft_status check_options(ft_handle *h, const ft_options *o) {
                     (long long)o->minibatch);
     if (o->reshuffle_each_epoch != 0 && o->reshuffle_each_epoch != 1)
         return fail(h, FT_EINVAL, "reshuffle_each_epoch must be 0 or 1");
+    if (o->vector_alu != 0 && o->vector_alu != 1)
+        return fail(h, FT_EINVAL, "vector_alu must be 0 or 1");
+    Shape vsh = h->sh;                  // the shape at the requested precision
+    vsh.prec = kF32;
+    if (o->vector_alu &&
+        (o->precision != FT_FP32 || !o->deterministic ||
+         !factor_valu_supported(vsh)))
+        return fail(h, FT_EINVAL,
+                    "vector_alu needs FP32 and the verify mode");
     return FT_OK;
 }
 
@@ -871,7 +881,10 @@ static ft_status run_minibatch(ft_handle *h, int64_t b, int apply,
     int nb = 0;
     {
         LaunchExt L(h, FT_K_FACTOR_GRAD);
-        HIPCHK(h, launch_factor_grad(h->sh, fa, &nb, h->stream));
+        if (h->opt.vector_alu)
+            HIPCHK(h, launch_factor_grad_valu(h->sh, fa, &nb, h->stream));
+        else
+            HIPCHK(h, launch_factor_grad(h->sh, fa, &nb, h->stream));
     }
     SegArgs sa{};
     sa.N = h->N;

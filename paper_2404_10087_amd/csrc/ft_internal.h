@@ -123,6 +123,12 @@ struct FactorArgs {
 hipError_t launch_factor_grad(const Shape &sh, const FactorArgs &a, int *nblocks,
                               hipStream_t s);
 int factor_grad_blocks(int32_t m);
+// The same outputs with the contractions on vector FP32 FMAs (one sample
+// per lane), for the matrix-core ablation; FP32 shapes with
+// N * max(J4, R16) <= 64 (factor_valu_supported).
+bool factor_valu_supported(const Shape &sh);
+hipError_t launch_factor_grad_valu(const Shape &sh, const FactorArgs &a,
+                                   int *nblocks, hipStream_t s);
 
 struct HogArgs {
     const uint16_t *A16[kMaxOrder];  // BF16 shadow of A (BF16 only)

@@ -342,6 +342,135 @@ __global__ __launch_bounds__(kFactorThreads) void hogwild_kernel(HogArgs a) {
     }
 }
 
+// ------------------------------------------------- vector-ALU factor kernel
+// The factor kernel's arithmetic with vector FP32 FMAs instead of the matrix
+// cores (for the ablation): one sample per lane; B^(1..N) staged in LDS and
+// read by every lane at the same address (broadcast). Per sample
+//     c^(n)_r = sum_j a^(n)_j B^(n)[j][r]           (all modes, in registers)
+//     d^(n)_r = prod_{m != n} c^(m)_r,   xhat = sum_r c^(1)_r d^(1)_r,
+//     g^(n)_j = (xhat - x) sum_r B^(n)[j][r] d^(n)_r,
+// with the factor rows streamed four elements at a time, and each gradient
+// row written to the sample's sorted slot like the matrix-core kernel.
+template <int N, int J4, int R16>
+__global__ __launch_bounds__(256) void factor_grad_valu_kernel(FactorArgs a) {
+    __shared__ float sB[N * J4 * R16];
+    const float *sBm[N];
+    stage_B<N, J4 * R16>(a.B, sB, sBm);
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    const bool valid = p < a.m;
+    const int ps = valid ? p : a.m - 1;
+    float C[N][R16];
+#pragma unroll
+    for (int n = 0; n < N; ++n) {
+        const float4 *ar =
+            reinterpret_cast<const float4 *>(a.A[n] + (int64_t)a.idx[n][ps] * J4);
+#pragma unroll
+        for (int r = 0; r < R16; ++r) C[n][r] = 0.f;
+        // the row loop stays rolled so that the mode and rank loops unroll
+        // fully and C stays in registers
+#pragma unroll 1
+        for (int jq = 0; jq < J4 / 4; ++jq) {
+            const float4 v = ar[jq];
+            const float av[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+#pragma unroll
+                for (int r = 0; r < R16; ++r)
+                    C[n][r] = fmaf(av[e], sBm[n][(4 * jq + e) * R16 + r], C[n][r]);
+        }
+    }
+    float xh = 0.f;
+#pragma unroll
+    for (int r = 0; r < R16; ++r) {
+        float prod = C[0][r];
+#pragma unroll
+        for (int n = 1; n < N; ++n) prod *= C[n][r];
+        xh += prod;
+    }
+    const float res = valid ? xh - a.val[ps] : 0.f;
+    const double loss = valid ? 0.5 * (double)res * (double)res : 0.0;
+    if (valid) {
+#pragma unroll
+        for (int n = 0; n < N; ++n) {
+            float d[R16];
+#pragma unroll
+            for (int r = 0; r < R16; ++r) {
+                float prod = 1.f;
+#pragma unroll
+                for (int m = 0; m < N; ++m)
+                    if (m != n) prod *= C[m][r];
+                d[r] = prod;
+            }
+            float4 *gr = reinterpret_cast<float4 *>(
+                a.G + ((int64_t)n * a.m + a.inv[n][p]) * J4);
+#pragma unroll 1
+            for (int jq = 0; jq < J4 / 4; ++jq) {
+                float g[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    float acc = 0.f;
+#pragma unroll
+                    for (int r = 0; r < R16; ++r)
+                        acc = fmaf(sBm[n][(4 * jq + e) * R16 + r], d[r], acc);
+                    g[e] = res * acc;
+                }
+                gr[jq] = make_float4(g[0], g[1], g[2], g[3]);
+            }
+        }
+    }
+    const double tot = block_sum_256(loss);
+    if (threadIdx.x == 0) a.loss_part[blockIdx.x] = tot;
+}
+
+bool factor_valu_supported(const Shape &sh) {
+    return sh.prec == kF32 && sh.N >= 2 && sh.N <= 5 && sh.J4 <= 32 &&
+           sh.R16 <= 32;
+}
+
+template <int N, int J4>
+static hipError_t launch_fgv_r(const Shape &sh, const FactorArgs &a, int blocks,
+                               hipStream_t s) {
+    if (sh.R16 == 16)
+        FT_LAUNCH((factor_grad_valu_kernel<N, J4, 16>), dim3(blocks), dim3(256),
+                  0, s, a);
+    else if (sh.R16 == 32)
+        FT_LAUNCH((factor_grad_valu_kernel<N, J4, 32>), dim3(blocks), dim3(256),
+                  0, s, a);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+template <int N>
+static hipError_t launch_fgv_j(const Shape &sh, const FactorArgs &a, int blocks,
+                               hipStream_t s) {
+    switch (sh.J4) {
+    case 4: return launch_fgv_r<N, 4>(sh, a, blocks, s);
+    case 8: return launch_fgv_r<N, 8>(sh, a, blocks, s);
+    case 12: return launch_fgv_r<N, 12>(sh, a, blocks, s);
+    case 16: return launch_fgv_r<N, 16>(sh, a, blocks, s);
+    case 20: return launch_fgv_r<N, 20>(sh, a, blocks, s);
+    case 24: return launch_fgv_r<N, 24>(sh, a, blocks, s);
+    case 28: return launch_fgv_r<N, 28>(sh, a, blocks, s);
+    case 32: return launch_fgv_r<N, 32>(sh, a, blocks, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_factor_grad_valu(const Shape &sh, const FactorArgs &a,
+                                   int *nblocks, hipStream_t s) {
+    if (!factor_valu_supported(sh)) return hipErrorInvalidValue;
+    const int blocks = (a.m + 255) / 256;
+    *nblocks = blocks;
+    switch (sh.N) {
+    case 2: return launch_fgv_j<2>(sh, a, blocks, s);
+    case 3: return launch_fgv_j<3>(sh, a, blocks, s);
+    case 4: return launch_fgv_j<4>(sh, a, blocks, s);
+    case 5: return launch_fgv_j<5>(sh, a, blocks, s);
+    }
+    return hipErrorInvalidValue;
+}
+
 template <int N, int KQ, int RB, int P>
 static hipError_t launch_fg(const FactorArgs &a, int blocks, hipStream_t s) {
     const int ntiles = (a.m + 15) / 16;

@@ -516,3 +516,39 @@ def test_epoch_builder_ahead_matches_injected_orders():
     A2, B2 = ft2.get_params()
     for a1, a2 in zip(A1 + B1, A2 + B2):
         assert np.array_equal(a1, a2)
+
+
+# ----------------------------------------------------------------- vector ALU
+@pytest.mark.parametrize("name", ["c0", "zipf", "hot", "order4",
+                                  "order5_J32_R32"])
+def test_vector_alu_factor_kernel_matches_oracle(name):
+    """The matrix-core ablation's factor kernel (vector FP32 FMAs, one sample
+    per lane) gives the same minibatch losses, row gradients and counts as
+    the oracle, to the same tolerance as the matrix-core kernel."""
+    w = W[name]
+    ft, T, A0, B0 = setup(w, with_test=False)
+    ft.set_options(vector_alu=1)
+    p = perm_for(w, T)
+    ft.set_epoch_order(p)
+    ft.prepare_epoch()
+    nmb = ft.num_minibatches()
+    for b in sorted({0, nmb - 1}):
+        loss, G, K = ft.factor_minibatch(b, apply=False)
+        idx, val = minibatch_slice(T, p, w.M, b)
+        oloss, OG, OK = oracle.factor_minibatch(f64(A0), f64(B0), idx, val,
+                                                w.lr_A, w.lam_A, w.row_mean,
+                                                apply=False, want_grad=True)
+        assert loss == pytest.approx(oloss, rel=LOSS_RTOL)
+        for n in range(w.order):
+            np.testing.assert_array_equal(K[n], OK[n])
+            assert rel_norm([G[n]], [OG[n]]) < GRAD_RTOL, (b, n)
+
+
+def test_vector_alu_rejects_unsupported_settings():
+    ft, _, _, _ = setup(W["c0"], with_test=False)
+    ft.set_options(precision=1)
+    with pytest.raises(FtError):
+        ft.set_options(vector_alu=1)          # BF16
+    ft.set_options(precision=0, deterministic=0)
+    with pytest.raises(FtError):
+        ft.set_options(vector_alu=1)          # Hogwild fast mode

@@ -85,10 +85,11 @@ typedef struct {
     uint64_t shuffle_seed;     /* seed of the device-side epoch order        */
     int32_t reshuffle_each_epoch; /* 1: new order every epoch; 0: fixed     */
     int32_t vector_alu;        /* 0: contractions on the matrix cores;
-                                  1: the factor kernel contracts with vector
-                                  FP32 FMAs instead (one sample per lane), for
-                                  the matrix-core ablation; FP32 and the
-                                  verify mode only (FT_EINVAL otherwise)    */
+                                  1: the factor and core kernels contract
+                                  with vector FP32 FMAs instead, for the
+                                  matrix-core ablation; FP32 and the verify
+                                  mode only (FT_EINVAL otherwise); the
+                                  stateless ft_mb_* calls ignore it         */
 } ft_options;
 
 /* Kernel classes that ft_profile_get reports. */

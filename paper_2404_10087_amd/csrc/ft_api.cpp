@@ -1132,7 +1132,10 @@ static ft_status core_pass(ft_handle *h, const int32_t *const *idx,
     ca.blocks_used = &used;
     {
         LaunchExt L(h, FT_K_CORE_GRAD);
-        HIPCHK(h, launch_core_grad(h->sh, ca, nb, h->stream));
+        if (h->opt.vector_alu)
+            HIPCHK(h, launch_core_grad_valu(h->sh, ca, nb, h->stream));
+        else
+            HIPCHK(h, launch_core_grad(h->sh, ca, nb, h->stream));
     }
     CoreUpdateArgs ua{};
     ua.part = h->core_part;

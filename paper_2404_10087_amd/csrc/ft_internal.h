@@ -124,8 +124,7 @@ hipError_t launch_factor_grad(const Shape &sh, const FactorArgs &a, int *nblocks
                               hipStream_t s);
 int factor_grad_blocks(int32_t m);
 // The same outputs with the contractions on vector FP32 FMAs (one sample
-// per lane), for the matrix-core ablation; FP32 shapes with
-// N * max(J4, R16) <= 64 (factor_valu_supported).
+// per lane), for the matrix-core ablation; FP32 only (factor_valu_supported).
 bool factor_valu_supported(const Shape &sh);
 hipError_t launch_factor_grad_valu(const Shape &sh, const FactorArgs &a,
                                    int *nblocks, hipStream_t s);
@@ -243,6 +242,10 @@ struct CoreArgs {
 int core_grad_blocks(int64_t count);
 hipError_t launch_core_grad(const Shape &sh, const CoreArgs &a, int nblocks,
                             hipStream_t s);
+// The same partials from vector FP32 FMAs (FP32 only; the ablation of the
+// matrix cores). The grid is capped by residency and by the chunk count.
+hipError_t launch_core_grad_valu(const Shape &sh, const CoreArgs &a,
+                                 int nblocks, hipStream_t s);
 
 struct CoreUpdateArgs {
     const float *part;    // [nblocks][N][J4][R16]

@@ -330,6 +330,215 @@ hipError_t launch_core_grad(const Shape &sh, const CoreArgs &a, int nblocks,
     return hipErrorInvalidValue;
 }
 
+// ------------------------------------------------- vector-ALU core kernel
+// The core kernel's arithmetic with vector FP32 FMAs instead of the matrix
+// cores (for the ablation). A persistent block sweeps chunks of S samples:
+//   1. TPS = 256 / S threads per sample split the rank range (r = sub + TPS k)
+//      and form their part of c^(n)_r = sum_j a^(n)_j B^(n)[j][r] (B staged in
+//      LDS); xhat is summed across the sample's threads by shuffles; each
+//      thread writes its d^(n)_r and a share of e^(n)_j = (xhat - x) a^(n)_j
+//      to LDS.
+//   2. Grad^(n) += e^(n)T d^(n) as register-blocked 4 x 4 outer products:
+//      thread u owns tile u mod T of the T = N (J4/4)(R16/4) tiles and the
+//      samples s = g, g + G, ... of the chunk, g = u / T (G = 256 / T groups
+//      when the tiles are fewer than the threads).
+// At the end each block sums its groups in increasing g and writes one
+// partial [N][J4][R16] in the layout of the matrix-core kernel, so the same
+// fixed-order update kernel finishes the step.
+template <int N, int J4, int R16>
+struct CoreValu {
+    static constexpr int S =
+        N * (J4 + R16) * 64 * 4 <= 32768 ? 64 : 32;   // samples per chunk
+    static constexpr int TPS = 256 / S;                 // threads per sample
+    static constexpr int RK = R16 / TPS;                // ranks per thread
+    static constexpr int T = N * (J4 / 4) * (R16 / 4);  // 4 x 4 tiles
+    static constexpr int G = T < 256 ? 256 / T : 1;     // sample groups
+    static constexpr int PAIRS = T * G;
+    static constexpr int PP = (PAIRS + 255) / 256;      // pairs per thread
+    static constexpr int WORK = S * N * (J4 + R16) > PAIRS * 16
+                                    ? S * N * (J4 + R16)
+                                    : PAIRS * 16;
+};
+
+template <int N, int J4, int R16>
+__global__ __launch_bounds__(256) void core_grad_valu_kernel(CoreArgs a,
+                                                             int64_t nchunks) {
+    using V = CoreValu<N, J4, R16>;
+    constexpr int S = V::S, TPS = V::TPS, RK = V::RK, T = V::T, G = V::G;
+    constexpr int TJ = J4 / 4, TR = R16 / 4;
+    __shared__ float4 sB4[N * J4 * R16 / 4];
+    __shared__ float4 work4[V::WORK / 4];
+    float *sB = reinterpret_cast<float *>(sB4);
+    float *sE = reinterpret_cast<float *>(work4);   // [S][N][J4]
+    float *sD = sE + S * N * J4;                    // [S][N][R16]
+    for (int e = threadIdx.x; e < N * J4 * R16; e += 256)
+        sB[e] = a.B[e / (J4 * R16)][e % (J4 * R16)];
+    __syncthreads();
+
+    const int s = threadIdx.x / TPS, sub = threadIdx.x % TPS;
+    float acc[V::PP][4][4];
+#pragma unroll
+    for (int pp = 0; pp < V::PP; ++pp)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) acc[pp][i][k] = 0.f;
+    double loss = 0.0;
+
+    for (int64_t chunk = blockIdx.x; chunk < nchunks; chunk += gridDim.x) {
+        const int64_t p = chunk * S + s;
+        const bool valid = p < a.count;
+        const int64_t ps = valid ? p : a.count - 1;
+        int rows[N];
+        float C[N][RK];
+#pragma unroll
+        for (int n = 0; n < N; ++n) {
+            rows[n] = a.idx[n][ps];
+            const float4 *ar =
+                reinterpret_cast<const float4 *>(a.A[n] + (int64_t)rows[n] * J4);
+            const float *bn = sB + n * J4 * R16 + sub;
+#pragma unroll
+            for (int k = 0; k < RK; ++k) C[n][k] = 0.f;
+#pragma unroll 1
+            for (int jq = 0; jq < J4 / 4; ++jq) {
+                const float4 v = ar[jq];
+                const float av[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+#pragma unroll
+                    for (int k = 0; k < RK; ++k)
+                        C[n][k] = fmaf(av[e], bn[(4 * jq + e) * R16 + TPS * k],
+                                       C[n][k]);
+            }
+        }
+        float xh = 0.f;
+#pragma unroll
+        for (int k = 0; k < RK; ++k) {
+            float prod = C[0][k];
+#pragma unroll
+            for (int n = 1; n < N; ++n) prod *= C[n][k];
+            xh += prod;
+        }
+#pragma unroll
+        for (int o = 1; o < TPS; o <<= 1) xh += __shfl_xor(xh, o);
+        const float res = valid ? xh - a.val[ps] : 0.f;
+        if (valid && sub == 0) loss += 0.5 * (double)res * (double)res;
+#pragma unroll
+        for (int n = 0; n < N; ++n) {
+#pragma unroll
+            for (int k = 0; k < RK; ++k) {
+                float prod = 1.f;
+#pragma unroll
+                for (int m = 0; m < N; ++m)
+                    if (m != n) prod *= C[m][k];
+                sD[(s * N + n) * R16 + sub + TPS * k] = prod;
+            }
+            const float *ar = a.A[n] + (int64_t)rows[n] * J4;
+            for (int j = sub; j < J4; j += TPS)
+                sE[(s * N + n) * J4 + j] = res * ar[j];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int pp = 0; pp < V::PP; ++pp) {
+            const int u = threadIdx.x + 256 * pp;
+            if (u < V::PAIRS) {
+                const int tile = u % T, g = u / T;
+                const int n = tile / (TJ * TR), jt = (tile / TR) % TJ,
+                          rt = tile % TR;
+                for (int s2 = g; s2 < S; s2 += G) {
+                    const float4 e4 = *reinterpret_cast<const float4 *>(
+                        sE + (s2 * N + n) * J4 + 4 * jt);
+                    const float4 d4 = *reinterpret_cast<const float4 *>(
+                        sD + (s2 * N + n) * R16 + 4 * rt);
+                    const float ev[4] = {e4.x, e4.y, e4.z, e4.w};
+                    const float dv[4] = {d4.x, d4.y, d4.z, d4.w};
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+#pragma unroll
+                        for (int k = 0; k < 4; ++k)
+                            acc[pp][i][k] = fmaf(ev[i], dv[k], acc[pp][i][k]);
+                }
+            }
+        }
+        __syncthreads();
+    }
+
+    float *red = reinterpret_cast<float *>(work4);   // [G][T][16]
+#pragma unroll
+    for (int pp = 0; pp < V::PP; ++pp) {
+        const int u = threadIdx.x + 256 * pp;
+        if (u < V::PAIRS)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int k = 0; k < 4; ++k) red[u * 16 + 4 * i + k] = acc[pp][i][k];
+    }
+    __syncthreads();
+    float *out = a.part + (int64_t)blockIdx.x * (N * J4 * R16);
+    for (int e = threadIdx.x; e < N * J4 * R16; e += 256) {
+        const int n = e / (J4 * R16), j = (e / R16) % J4, r = e % R16;
+        const int tile = (n * TJ + j / 4) * TR + r / 4;
+        const int inner = 4 * (j % 4) + r % 4;
+        float sum = 0.f;
+        for (int g = 0; g < G; ++g) sum += red[(g * T + tile) * 16 + inner];
+        out[e] = sum;
+    }
+    const double tot = block_sum_256(loss);
+    if (threadIdx.x == 0) a.loss_part[blockIdx.x] = tot;
+}
+
+template <int N, int J4, int R16>
+static hipError_t launch_cgv(const CoreArgs &a, int blocks, hipStream_t s) {
+    using V = CoreValu<N, J4, R16>;
+    const int64_t nchunks = (a.count + V::S - 1) / V::S;
+    const int fit = resident_blocks(
+        reinterpret_cast<const void *>(&core_grad_valu_kernel<N, J4, R16>), 0);
+    if (blocks > fit) blocks = fit;
+    if (blocks > nchunks) blocks = (int)nchunks;
+    if (blocks < 1) blocks = 1;
+    *a.blocks_used = blocks;
+    FT_LAUNCH((core_grad_valu_kernel<N, J4, R16>), dim3(blocks), dim3(256), 0,
+              s, a, nchunks);
+    return hipGetLastError();
+}
+
+template <int N, int J4>
+static hipError_t launch_cgv_r(const Shape &sh, const CoreArgs &a, int blocks,
+                               hipStream_t s) {
+    if (sh.R16 == 16) return launch_cgv<N, J4, 16>(a, blocks, s);
+    if (sh.R16 == 32) return launch_cgv<N, J4, 32>(a, blocks, s);
+    return hipErrorInvalidValue;
+}
+
+template <int N>
+static hipError_t launch_cgv_j(const Shape &sh, const CoreArgs &a, int blocks,
+                               hipStream_t s) {
+    switch (sh.J4) {
+    case 4: return launch_cgv_r<N, 4>(sh, a, blocks, s);
+    case 8: return launch_cgv_r<N, 8>(sh, a, blocks, s);
+    case 12: return launch_cgv_r<N, 12>(sh, a, blocks, s);
+    case 16: return launch_cgv_r<N, 16>(sh, a, blocks, s);
+    case 20: return launch_cgv_r<N, 20>(sh, a, blocks, s);
+    case 24: return launch_cgv_r<N, 24>(sh, a, blocks, s);
+    case 28: return launch_cgv_r<N, 28>(sh, a, blocks, s);
+    case 32: return launch_cgv_r<N, 32>(sh, a, blocks, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_core_grad_valu(const Shape &sh, const CoreArgs &a,
+                                 int nblocks, hipStream_t s) {
+    if (sh.prec != kF32) return hipErrorInvalidValue;
+    if (nblocks > kCoreMaxBlocks) nblocks = kCoreMaxBlocks;
+    switch (sh.N) {
+    case 2: return launch_cgv_j<2>(sh, a, nblocks, s);
+    case 3: return launch_cgv_j<3>(sh, a, nblocks, s);
+    case 4: return launch_cgv_j<4>(sh, a, nblocks, s);
+    case 5: return launch_cgv_j<5>(sh, a, nblocks, s);
+    }
+    return hipErrorInvalidValue;
+}
+
 // 64 consecutive elements per block; four slices of the partials each summed
 // in increasing block order, then the slices in order.
 // One block per 32 consecutive elements of [N][J4][R16]; thread (slice sl,

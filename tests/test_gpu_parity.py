@@ -544,6 +544,50 @@ def test_vector_alu_factor_kernel_matches_oracle(name):
             assert rel_norm([G[n]], [OG[n]]) < GRAD_RTOL, (b, n)
 
 
+@pytest.mark.parametrize("name", ["c0", "pad_J3_R5", "order2", "order4",
+                                  "order5_J32_R32", "J12_R20", "zipf"])
+def test_vector_alu_core_gradient_matches_oracle(name):
+    """The matrix-core ablation's core kernel (register-blocked outer
+    products on vector FMAs) gives the oracle's core loss, gradient and
+    update."""
+    w = W[name]
+    ft, T, A0, B0 = setup(w, with_test=False)
+    ft.set_options(vector_alu=1)
+    A, B = f64(A0), f64(B0)
+    tv = T.train_val.astype(np.float64)
+    loss, G = ft.core_grad()
+    oloss, OG = oracle.core_grad(A, B, T.train_idx, tv)
+    assert loss == pytest.approx(oloss, rel=LOSS_RTOL)
+    for n in range(w.order):
+        assert rel_norm([G[n]], [OG[n]]) < GRAD_RTOL, n
+    cl = ft.epoch_core()
+    assert cl == pytest.approx(oloss, rel=LOSS_RTOL)
+    oracle.core_epoch(A, B, T.train_idx, tv, w.lr_B, w.lam_B)
+    _, B1 = ft.get_params()
+    for n in range(w.order):
+        d_gpu = B1[n].astype(np.float64) - B0[n]
+        d_orc = B[n] - B0[n]
+        tol = GRAD_RTOL * np.linalg.norm(d_orc) + \
+            2 * EPS32 * np.linalg.norm(B[n])
+        assert np.linalg.norm(d_gpu - d_orc) <= tol, n
+
+
+def test_vector_alu_core_per_minibatch_steps():
+    w = W["c0"]
+    ft, T, A0, B0 = setup(w, with_test=False)
+    ft.set_options(core_step=FT_CORE_PER_MINIBATCH, vector_alu=1)
+    p = perm_for(w, T, 2)
+    ft.set_epoch_order(p)
+    A, B = f64(A0), f64(B0)
+    tv = T.train_val.astype(np.float64)
+    cl = ft.epoch_core()
+    ocl = oracle.core_epoch(A, B, T.train_idx, tv, w.lr_B, w.lam_B, perm=p,
+                            M=w.M, per_minibatch=True)
+    assert cl == pytest.approx(ocl, rel=RMSE_RTOL)
+    _, B1 = ft.get_params()
+    assert rel_norm(B1, B) < RMSE_RTOL
+
+
 def test_vector_alu_rejects_unsupported_settings():
     ft, _, _, _ = setup(W["c0"], with_test=False)
     ft.set_options(precision=1)

@@ -51,7 +51,10 @@ __device__ __forceinline__ float bf2f(uint16_t h) {
 // FP8 e4m3 quantisation with one FP32 scale per vector: s = max|x| / 448
 // (448 is the largest e4m3 value), q = e4m3(x * (448 / max|x|)) rounded to
 // nearest even by the hardware conversion, clamped to +-448 first; x is
-// represented as s * q. An all-zero vector gets s = 0 and zero codes.
+// represented as s * q. An all-zero vector gets s = 0 and zero codes. A
+// vector holding a NaN or an infinity gets a NaN scale (fmaxf would drop a
+// NaN and the clamp would turn it into a finite code), so non-finite
+// parameters stay visible in the losses computed from the shadow.
 constexpr float kFP8Max = 448.f;
 __device__ __forceinline__ uint32_t fp8x4(float a, float b, float c, float d) {
     const uint32_t w = __builtin_amdgcn_cvt_pk_fp8_f32(a, b, 0u, false);
@@ -78,16 +81,19 @@ __device__ __forceinline__ float fp8_byte(uint64_t w, int e) {
 template <int J4>
 __device__ __forceinline__ void quantize_row_fp8(const float (&x)[J4],
                                                  uint8_t *dst, float *sdst) {
-    float m = 0.f;
+    float m = 0.f, nf = 0.f;
 #pragma unroll
-    for (int j = 0; j < J4; ++j) m = fmaxf(m, fabsf(x[j]));
+    for (int j = 0; j < J4; ++j) {
+        m = fmaxf(m, fabsf(x[j]));
+        nf += x[j] * 0.f;   // NaN if x[j] is NaN or infinite
+    }
     const float inv = fp8_prescale(m);
     uint32_t *d = reinterpret_cast<uint32_t *>(dst);
 #pragma unroll
     for (int j = 0; j < J4; j += 4)
         d[j / 4] = fp8x4(fp8_clamp(x[j] * inv), fp8_clamp(x[j + 1] * inv),
                          fp8_clamp(x[j + 2] * inv), fp8_clamp(x[j + 3] * inv));
-    *sdst = m / kFP8Max;
+    *sdst = m / kFP8Max + nf;
 }
 
 // Where a tile reads factor rows from: the FP32 master and the BF16 or FP8
@@ -209,14 +215,17 @@ struct ColFrag<KQ, kFP8> {
     __device__ __forceinline__ void load(const float *B, int R16, int q,
                                          int col) {
         float x[KQ];
-        float m = 0.f;
+        float m = 0.f, nf = 0.f;
 #pragma unroll
         for (int t = 0; t < KQ; ++t) {
             x[t] = B[(KQ * q + t) * R16 + col];
             m = fmaxf(m, fabsf(x[t]));
+            nf += x[t] * 0.f;   // NaN if x[t] is NaN or infinite
         }
         m = fmaxf(m, __shfl_xor(m, 16));
         m = fmaxf(m, __shfl_xor(m, 32));
+        nf += __shfl_xor(nf, 16);
+        nf += __shfl_xor(nf, 32);
         const float inv = fp8_prescale(m);
         uint64_t w = 0;
 #pragma unroll
@@ -228,7 +237,7 @@ struct ColFrag<KQ, kFP8> {
             w |= (uint64_t)fp8x4(x0, x1, x2, x3) << (8 * t);
         }
         v[0] = (long)w;
-        s = m / kFP8Max;
+        s = m / kFP8Max + nf;
     }
 };
 

@@ -269,11 +269,22 @@ def test_zero_learning_rate_leaves_parameters():
     assert ft.loss(FT_TRAIN) == l0
 
 
-def test_nonfinite_parameter_is_reported():
+@pytest.mark.parametrize("prec", [0, 1, 2])
+@pytest.mark.parametrize("where", ["A", "B"])
+@pytest.mark.parametrize("value", [np.nan, np.inf])
+def test_nonfinite_parameter_is_reported(prec, where, value):
+    """A NaN or an infinity in a factor or core matrix makes the epoch fail
+    with FT_ENONFINITE in every contraction precision (the low-precision
+    shadows and operands must not turn it into a finite code)."""
     w = W["c0"]
     ft, T, A0, B0 = setup(w, with_test=False)
-    A0[1][3, 2] = np.nan
-    ft.set_params(A=A0)
+    ft.set_options(precision=prec)
+    if where == "A":
+        A0[1][3, 2] = value
+        ft.set_params(A=A0)
+    else:
+        B0[2][1, 3] = value
+        ft.set_params(B=B0)
     with pytest.raises(FtError) as e:
         ft.epoch_factors()
     assert e.value.status == 5

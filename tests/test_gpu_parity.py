@@ -531,7 +531,8 @@ def test_epoch_builder_ahead_matches_injected_orders():
 
 # ----------------------------------------------------------------- vector ALU
 @pytest.mark.parametrize("name", ["c0", "zipf", "hot", "order4",
-                                  "order5_J32_R32"])
+                                  "order5_J32_R32", "M1", "nnz_lt_M",
+                                  "pad_J3_R5"])
 def test_vector_alu_factor_kernel_matches_oracle(name):
     """The matrix-core ablation's factor kernel (vector FP32 FMAs, one sample
     per lane) gives the same minibatch losses, row gradients and counts as
@@ -556,7 +557,8 @@ def test_vector_alu_factor_kernel_matches_oracle(name):
 
 
 @pytest.mark.parametrize("name", ["c0", "pad_J3_R5", "order2", "order4",
-                                  "order5_J32_R32", "J12_R20", "zipf"])
+                                  "order5_J32_R32", "J12_R20", "zipf", "M1",
+                                  "nnz_lt_M"])
 def test_vector_alu_core_gradient_matches_oracle(name):
     """The matrix-core ablation's core kernel (register-blocked outer
     products on vector FMAs) gives the oracle's core loss, gradient and

@@ -234,8 +234,21 @@ __device__ __forceinline__ void stage_B(const float *const *B, float *sB,
 
 // Each wave sweeps kFactorTilesPerWave tiles and issues the next tile's
 // index and row loads before the current tile's arithmetic.
+// Waves per SIMD the register allocator is asked to reach. Without a hint
+// it reserves accumulator registers apart and lands one wave lower on most
+// shapes; two is reached by every shape without spilling, three by the
+// order-4 J = R = 32 and order-5 J = 32, R = 16 FP32 tiles (checked per
+// instantiation at build time: no spills, no scratch).
+constexpr int factor_waves(int N, int KQ, int RB, int P) {
+    return (P == kF32 && KQ == 8 && ((N == 4 && RB == 2) || (N == 5 && RB == 1)))
+               ? 3
+               : 2;
+}
+
 template <int N, int KQ, int RB, int P>
-__global__ __launch_bounds__(kFactorThreads) void factor_grad_kernel(
+__global__ __launch_bounds__(kFactorThreads)
+__attribute__((amdgpu_waves_per_eu(factor_waves(N, KQ, RB, P)))) void
+factor_grad_kernel(
     FactorArgs a, int ntiles) {
     using T = FactorTile<N, KQ, RB, P>;
     __shared__ float sB[N * T::J4 * T::R16];

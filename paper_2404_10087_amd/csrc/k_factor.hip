@@ -236,14 +236,11 @@ __device__ __forceinline__ void stage_B(const float *const *B, float *sB,
 // index and row loads before the current tile's arithmetic.
 // Waves per SIMD the register allocator is asked to reach. Without a hint
 // it reserves accumulator registers apart and lands one wave lower on most
-// shapes; two is reached by every shape without spilling, three by the
-// order-4 J = R = 32 and order-5 J = 32, R = 16 FP32 tiles (checked per
-// instantiation at build time: no spills, no scratch).
-constexpr int factor_waves(int N, int KQ, int RB, int P) {
-    return (P == kF32 && KQ == 8 && ((N == 4 && RB == 2) || (N == 5 && RB == 1)))
-               ? 3
-               : 2;
-}
+// shapes; two is reached by every shape without spilling or scratch
+// (checked per instantiation at build time). Asking for three where it
+// fits (order 4, J = R = 32) made the kernel faster but slowed the builder
+// running beside it, and the epoch with it.
+constexpr int factor_waves(int, int, int, int) { return 2; }
 
 template <int N, int KQ, int RB, int P>
 __global__ __launch_bounds__(kFactorThreads)

@@ -38,6 +38,46 @@ MUTANTS = {
         ("a[j] -= lrA * (gr[j] * scale);", "a[j] += lrA * (gr[j] * scale);"),
     "regulariser of Eq. (4) on mode 0 only":
         ("na += A[n][e] * A[n][e];", "na += n == 0 ? A[n][e] * A[n][e] : 0.0;"),
+    "tail minibatch of the factor epoch dropped":
+        ("for (int64_t first = 0; first < nnz; first += M, ++b) {",
+         "for (int64_t first = 0; first + M <= nnz; first += M, ++b) {"),
+    "per-minibatch core step divided by M instead of the slice size":
+        ("B[n][e] -= lrB * (Grad[n][e] / (double)m + lamB * B[n][e]);",
+         "B[n][e] -= lrB * (Grad[n][e] / (double)M + lamB * B[n][e]);"),
+    "B held fixed across the per-minibatch core steps":
+        ("loss += orc_core_grad(N, J, R, A, B, m, bidx, bvals, Grad);",
+         "static double *Bs[ORC_MAX_ORDER];\n"
+         "            if (first == 0)\n"
+         "                for (int n = 0; n < N; ++n) {\n"
+         "                    Bs[n] = malloc(sizeof(double) * J[n] * (size_t)R);\n"
+         "                    memcpy(Bs[n], B[n], sizeof(double) * J[n] * (size_t)R);\n"
+         "                }\n"
+         "            loss += orc_core_grad(N, J, R, A, Bs, m, bidx, bvals, Grad);"),
+    "A held fixed across the factor minibatches":
+        ("double l = orc_factor_minibatch(N, dims, J, R, A, B, m, bidx, bvals,\n"
+         "                                        lrA, lamA, row_mean, 1, NULL, NULL);",
+         "static double *As[ORC_MAX_ORDER];\n"
+         "        if (first == 0)\n"
+         "            for (int n = 0; n < N; ++n) {\n"
+         "                As[n] = malloc(sizeof(double) * dims[n] * J[n]);\n"
+         "                memcpy(As[n], A[n], sizeof(double) * dims[n] * J[n]);\n"
+         "            }\n"
+         "        double l = orc_factor_minibatch(N, dims, J, R, As, B, m, bidx, bvals,\n"
+         "                                        lrA, lamA, row_mean, 0, NULL, NULL);\n"
+         "        {\n"
+         "            double *Gd[ORC_MAX_ORDER]; int64_t *Kd[ORC_MAX_ORDER];\n"
+         "            for (int n = 0; n < N; ++n) {\n"
+         "                Gd[n] = calloc((size_t)(dims[n] * J[n]), sizeof(double));\n"
+         "                Kd[n] = calloc((size_t)dims[n], sizeof(int64_t));\n"
+         "            }\n"
+         "            orc_factor_minibatch(N, dims, J, R, As, B, m, bidx, bvals,\n"
+         "                                 lrA, lamA, row_mean, 0, Gd, Kd);\n"
+         "            for (int n = 0; n < N; ++n)\n"
+         "                for (int64_t i = 0; i < dims[n]; ++i)\n"
+         "                    for (int32_t j = 0; j < J[n]; ++j)\n"
+         "                        if (Kd[n][i]) A[n][i * J[n] + j] -= lrA * Gd[n][i * J[n] + j]\n"
+         "                            / (row_mean ? (double)Kd[n][i] : 1.0);\n"
+         "        }"),
     "Gauss-Seidel rows within the minibatch":
         ("gr[j] += r * bd + lamA * a[j];",
          "gr[j] += r * bd + lamA * a[j];\n                if (apply) ((double *)a)[j] -= lrA * (r * bd + lamA * a[j]);"),
@@ -60,6 +100,14 @@ def run_pins():
         "loss": lambda: pins.test_loss_and_residual_stats_definitions(oracle),
         "core": lambda: pins.test_core_epoch_step_matches_autograd(oracle),
         "P8": lambda: pins.test_p8_core_epoch_order_invariance(oracle),
+        "split-sum": lambda:
+            pins.test_factor_epoch_splits_into_minibatches_with_tail(
+                oracle, False),
+        "split-mean": lambda:
+            pins.test_factor_epoch_splits_into_minibatches_with_tail(
+                oracle, True),
+        "core-split": lambda:
+            pins.test_core_epoch_per_minibatch_steps_with_tail(oracle),
     }
     for name, fn in checks.items():
         try:

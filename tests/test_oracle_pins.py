@@ -381,3 +381,66 @@ def test_core_epoch_step_matches_autograd(oracle_mod):
     for n in range(3):
         np.testing.assert_allclose(B1[n], B[n] - lr * (gB[n] / 90 + lam * B[n]),
                                    rtol=1e-11, atol=1e-13)
+
+
+# ----------------------------- minibatch split of an epoch (Algorithm 3) ----
+def _slices(nnz, M):
+    return [(f, min(f + M, nnz)) for f in range(0, nnz, M)]
+
+
+@pytest.mark.parametrize("row_mean", [False, True])
+def test_factor_epoch_splits_into_minibatches_with_tail(oracle_mod, row_mean):
+    """Algorithm 3's factor loop over one permutation pass: consecutive
+    slices of M samples of the order, the last one shorter (25 samples,
+    M = 7: slices 7, 7, 7, 4), each a Jacobi step from the parameters left
+    by the previous slice. Reference: per-slice gradients from torch
+    autograd through the dense-Tucker graph (Eq. (12) summed per row, or
+    divided by the row's occurrence count in the slice)."""
+    dims, J, R = (5, 4, 6), (3, 2, 4), 3
+    A, B, idx, vals = rand_problem(dims, J, R, 25, 41)
+    lr, lam, M = 0.04, 0.02, 7
+    perm = np.random.default_rng(7).permutation(25)
+    Ao = [a.copy() for a in A]
+    mb = oracle_mod.factor_epoch(Ao, B, idx, vals, perm, M, lr, lam, row_mean)
+    assert mb.shape == (4,)
+    Ar = [a.copy() for a in A]
+    ref_losses = []
+    for f, e in _slices(25, M):
+        sel = perm[f:e]
+        sidx = np.ascontiguousarray(idx[:, sel])
+        gA, _, l = torch_minibatch_grads(Ar, B, sidx, vals[sel], lam)
+        ref_losses.append(l)
+        for n in range(3):
+            k = np.bincount(sidx[n], minlength=dims[n])[:, None]
+            step = gA[n] / np.maximum(k, 1) if row_mean else gA[n]
+            Ar[n] = Ar[n] - lr * step
+    np.testing.assert_allclose(mb, ref_losses, rtol=1e-11)
+    for n in range(3):
+        np.testing.assert_allclose(Ao[n], Ar[n], rtol=1e-11, atol=1e-13)
+
+
+def test_core_epoch_per_minibatch_steps_with_tail(oracle_mod):
+    """The per-minibatch core step (Algorithm 3's second loop with the
+    minibatch mean of Eq. (5)) over four slices of the order (7, 7, 7, 4):
+    B <- B - lr_B (Grad_slice / |slice| + lambda_B B) after every slice,
+    with Grad_slice the autograd gradient of sum r^2/2 over the slice at
+    the current B and A held fixed. The returned loss sums each slice's
+    loss at the B in force when it was visited."""
+    dims, J, R = (6, 5, 4), (3, 2, 4), 3
+    A, B, idx, vals = rand_problem(dims, J, R, 25, 43)
+    lr, lam, M = 0.3, 0.05, 7
+    perm = np.random.default_rng(8).permutation(25)
+    Bo = [b.copy() for b in B]
+    lo = oracle_mod.core_epoch(A, Bo, idx, vals, lr, lam, perm=perm, M=M,
+                               per_minibatch=True)
+    Br = [b.copy() for b in B]
+    lref = 0.0
+    for f, e in _slices(25, M):
+        sel = perm[f:e]
+        _, gB, l = torch_minibatch_grads(A, Br, np.ascontiguousarray(
+            idx[:, sel]), vals[sel], 0.0)
+        lref += l
+        Br = [Br[n] - lr * (gB[n] / (e - f) + lam * Br[n]) for n in range(3)]
+    assert lo == pytest.approx(lref, rel=1e-11)
+    for n in range(3):
+        np.testing.assert_allclose(Bo[n], Br[n], rtol=1e-11, atol=1e-13)

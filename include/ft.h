@@ -272,6 +272,33 @@ ft_status ft_mb_backward(const ft_problem_desc *p, const float *const *A,
                          int64_t *n_uniq_dev, float *const *gradB,
                          void *workspace, size_t ws_bytes, void *hip_stream);
 
+/* ------------------------------------------------------------------------
+ * Allocation-free backward. For callers that cannot allocate device memory
+ * during the call: code under HIP graph capture, tight serving or training
+ * loops, harnesses that forbid hipMalloc. Same arguments, outputs and
+ * results as ft_mb_backward, without the workspace: the intermediates live
+ * in a static device array of FT_NOALLOC_SCRATCH_BYTES (64 MiB) that every
+ * device the library runs on holds from its first use until the process
+ * ends. The call allocates nothing (no hipMalloc, hipFree or allocating
+ * library routine); its address is looked up once per device
+ * (hipGetSymbolAddress) on the first call made with that device current.
+ * A minibatch whose workspace (ft_mb_workspace_size) exceeds the array is
+ * rejected with FT_EINVAL before any device work. All calls on one device
+ * share the one array: calls that may overlap on a device (other streams,
+ * other host threads) race and give wrong results; serialise them. The
+ * array keeps the last call's contents; nothing in it needs to start zero.
+ * ------------------------------------------------------------------------ */
+#define FT_NOALLOC_SCRATCH_BYTES (64ull << 20)
+
+ft_status ft_mb_backward_noalloc(const ft_problem_desc *p,
+                                 const float *const *A, const float *const *B,
+                                 const int32_t *const *idx, const float *val,
+                                 int64_t m, const float *grad_out_dev,
+                                 float *const *gradA,
+                                 int32_t *const *uniq_rows,
+                                 float *const *uniq_grad, int64_t *n_uniq_dev,
+                                 float *const *gradB, void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

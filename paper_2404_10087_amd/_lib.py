@@ -82,7 +82,13 @@ SIGNATURES = {
                                  C.c_void_p, C.c_void_p, C.c_void_p,
                                  C.c_void_p, C.c_void_p, C.c_size_t,
                                  C.c_void_p]),
+    "ft_mb_backward_noalloc": (C.c_int, [C.POINTER(ProblemDesc), C.c_void_p,
+                                         C.c_void_p, C.c_void_p, C.c_void_p,
+                                         C.c_int64, C.c_void_p, C.c_void_p,
+                                         C.c_void_p, C.c_void_p, C.c_void_p,
+                                         C.c_void_p, C.c_void_p]),
 }
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 _lib = None
 

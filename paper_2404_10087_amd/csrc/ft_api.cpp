@@ -13,6 +13,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1501,14 +1502,14 @@ extern "C" ft_status ft_mb_workspace_size(const ft_problem_desc *p, int64_t m,
     return FT_OK;
 }
 
-static ft_status check_mb_args(const ft_problem_desc *p, const float *const *A,
-                               const float *const *B, const int32_t *const *idx,
-                               const float *val, int64_t m, void *ws,
-                               size_t ws_bytes) {
+static ft_status check_mb_inputs(const ft_problem_desc *p,
+                                 const float *const *A, const float *const *B,
+                                 const int32_t *const *idx, const float *val,
+                                 int64_t m) {
     ft_status st = check_desc(p, m);
     if (st != FT_OK) return st;
-    if (!A || !B || !idx || !val || !ws)
-        return fail(nullptr, FT_EINVAL, "A, B, idx, val or workspace is NULL");
+    if (!A || !B || !idx || !val)
+        return fail(nullptr, FT_EINVAL, "A, B, idx or val is NULL");
     for (int n = 0; n < p->order; ++n) {
         if (!A[n] || !B[n] || !idx[n])
             return fail(nullptr, FT_EINVAL, "A[%d], B[%d] or idx[%d] is NULL",
@@ -1516,6 +1517,16 @@ static ft_status check_mb_args(const ft_problem_desc *p, const float *const *A,
         if (reinterpret_cast<uintptr_t>(A[n]) % 16)
             return fail(nullptr, FT_EINVAL, "A[%d] is not 16-byte aligned", n);
     }
+    return FT_OK;
+}
+
+static ft_status check_mb_args(const ft_problem_desc *p, const float *const *A,
+                               const float *const *B, const int32_t *const *idx,
+                               const float *val, int64_t m, void *ws,
+                               size_t ws_bytes) {
+    ft_status st = check_mb_inputs(p, A, B, idx, val, m);
+    if (st != FT_OK) return st;
+    if (!ws) return fail(nullptr, FT_EINVAL, "workspace is NULL");
     if (reinterpret_cast<uintptr_t>(ws) % 256)
         return fail(nullptr, FT_EINVAL, "workspace is not 256-byte aligned");
     const size_t need = mb_layout(p, m).bytes;
@@ -1553,14 +1564,12 @@ extern "C" ft_status ft_mb_forward(const ft_problem_desc *p,
     return FT_OK;
 }
 
-extern "C" ft_status ft_mb_backward(
-    const ft_problem_desc *p, const float *const *A, const float *const *B,
-    const int32_t *const *idx, const float *val, int64_t m,
-    const float *grad_out_dev, float *const *gradA, int32_t *const *uniq_rows,
-    float *const *uniq_grad, int64_t *n_uniq_dev, float *const *gradB,
-    void *workspace, size_t ws_bytes, void *hip_stream) {
-    ft_status st = check_mb_args(p, A, B, idx, val, m, workspace, ws_bytes);
-    if (st != FT_OK) return st;
+static ft_status check_backward_outputs(const ft_problem_desc *p,
+                                        float *const *gradA,
+                                        int32_t *const *uniq_rows,
+                                        float *const *uniq_grad,
+                                        int64_t *n_uniq_dev,
+                                        float *const *gradB) {
     if (!gradB) return fail(nullptr, FT_EINVAL, "gradB is NULL");
     const bool sparse = uniq_rows && uniq_grad && n_uniq_dev;
     if ((uniq_rows || uniq_grad || n_uniq_dev) && !sparse)
@@ -1573,7 +1582,20 @@ extern "C" ft_status ft_mb_backward(
         if (sparse && (!uniq_rows[n] || !uniq_grad[n]))
             return fail(nullptr, FT_EINVAL, "uniq_rows/grad[%d] is NULL", n);
     }
-    hipStream_t s = (hipStream_t)hip_stream;
+    return FT_OK;
+}
+
+// The backward kernels of one minibatch on the stream s, with every
+// intermediate in the workspace ws (mb_layout(p, m).bytes, 256-byte
+// aligned). Arguments are already validated.
+static ft_status mb_backward_run(
+    const ft_problem_desc *p, const float *const *A, const float *const *B,
+    const int32_t *const *idx, const float *val, int64_t m,
+    const float *grad_out_dev, float *const *gradA, int32_t *const *uniq_rows,
+    float *const *uniq_grad, int64_t *n_uniq_dev, float *const *gradB,
+    void *workspace, hipStream_t s) {
+    const bool sparse = uniq_rows && uniq_grad && n_uniq_dev;
+    ft_status st = FT_OK;
     const MbLayout L = mb_layout(p, m);
     const int N = p->order;
     const float *Bp[kMaxOrder] = {};
@@ -1719,4 +1741,79 @@ extern "C" ft_status ft_mb_backward(
     }
     HIPCHK0(launch_core_update(L.sh, ua, s));
     return FT_OK;
+}
+
+extern "C" ft_status ft_mb_backward(
+    const ft_problem_desc *p, const float *const *A, const float *const *B,
+    const int32_t *const *idx, const float *val, int64_t m,
+    const float *grad_out_dev, float *const *gradA, int32_t *const *uniq_rows,
+    float *const *uniq_grad, int64_t *n_uniq_dev, float *const *gradB,
+    void *workspace, size_t ws_bytes, void *hip_stream) {
+    ft_status st = check_mb_args(p, A, B, idx, val, m, workspace, ws_bytes);
+    if (st != FT_OK) return st;
+    st = check_backward_outputs(p, gradA, uniq_rows, uniq_grad, n_uniq_dev,
+                                gradB);
+    if (st != FT_OK) return st;
+    return mb_backward_run(p, A, B, idx, val, m, grad_out_dev, gradA,
+                           uniq_rows, uniq_grad, n_uniq_dev, gradB, workspace,
+                           (hipStream_t)hip_stream);
+}
+
+// ------------------------------------------------- allocation-free backward
+// Workspace of ft_mb_backward_noalloc: one array per device, resident from
+// the library's first use on that device until the process ends. In host
+// code the array's name is not a device address; its address on the current
+// device comes from hipGetSymbolAddress, taken once per device and kept in
+// g_scratch_dev.
+static __device__ __align__(256) unsigned char scratch[FT_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_dev[kScratchDevices] = {};
+}  // namespace
+
+static ft_status scratch_on_current_device(void **out) {
+    int dev = -1;
+    HIPCHK0(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kScratchDevices)
+        return fail(nullptr, FT_EDEVICE, "device %d beyond the %d supported",
+                    dev, kScratchDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(nullptr, FT_EDEVICE,
+                        "hipGetSymbolAddress(scratch) on device %d: %s", dev,
+                        hipGetErrorString(e));
+        g_scratch_dev[dev] = ptr;
+    }
+    *out = g_scratch_dev[dev];
+    return FT_OK;
+}
+
+extern "C" ft_status ft_mb_backward_noalloc(
+    const ft_problem_desc *p, const float *const *A, const float *const *B,
+    const int32_t *const *idx, const float *val, int64_t m,
+    const float *grad_out_dev, float *const *gradA, int32_t *const *uniq_rows,
+    float *const *uniq_grad, int64_t *n_uniq_dev, float *const *gradB,
+    void *hip_stream) {
+    ft_status st = check_mb_inputs(p, A, B, idx, val, m);
+    if (st != FT_OK) return st;
+    st = check_backward_outputs(p, gradA, uniq_rows, uniq_grad, n_uniq_dev,
+                                gradB);
+    if (st != FT_OK) return st;
+    const size_t need = mb_layout(p, m).bytes;
+    if (need > (size_t)FT_NOALLOC_SCRATCH_BYTES)
+        return fail(nullptr, FT_EINVAL,
+                    "minibatch needs %zu bytes of workspace, more than the "
+                    "%zu of the static scratch (use ft_mb_backward)",
+                    need, (size_t)FT_NOALLOC_SCRATCH_BYTES);
+    void *ws = nullptr;
+    st = scratch_on_current_device(&ws);
+    if (st != FT_OK) return st;
+    return mb_backward_run(p, A, B, idx, val, m, grad_out_dev, gradA,
+                           uniq_rows, uniq_grad, n_uniq_dev, gradB, ws,
+                           (hipStream_t)hip_stream);
 }

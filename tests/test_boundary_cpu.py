@@ -101,3 +101,28 @@ def test_minibatch_sort_reference_is_stable():
     pos, srt = _ref.minibatch_sort(rows)
     assert list(pos) == [6, 3, 1, 4, 5, 0, 2]
     assert list(srt) == [0, 1, 3, 3, 3, 5, 5]
+
+
+def test_noalloc_backward_rejects_oversized_minibatch_before_device_work():
+    lib = _lib.load()
+    d = _lib.ProblemDesc()
+    d.order = 3
+    for n in range(3):
+        d.dims[n] = 1000
+        d.J[n] = 16
+    d.R = 16
+    m = 2_000_000
+    nbytes = C.c_size_t()
+    assert lib.ft_mb_workspace_size(C.byref(d), m, C.byref(nbytes)) == 0
+    assert nbytes.value > _lib.NOALLOC_SCRATCH_BYTES
+    fake = (C.c_void_p * 3)(*[C.c_void_p(256 * (k + 1)) for k in range(3)])
+    st = lib.ft_mb_backward_noalloc(C.byref(d), fake, fake, fake,
+                                    C.c_void_p(256), m, None, None, None,
+                                    None, None, fake, None)
+    assert st == _lib.FT_EINVAL
+    assert b"static scratch" in lib.ft_last_error(None)
+    # and a NULL output is caught before the size
+    st = lib.ft_mb_backward_noalloc(C.byref(d), fake, fake, fake,
+                                    C.c_void_p(256), 100, None, None, None,
+                                    None, None, None, None)
+    assert st == _lib.FT_EINVAL

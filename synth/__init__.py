@@ -6,6 +6,6 @@ gradient, an update, a residual or a loss.
 """
 from .gen import (  # noqa: F401
     Tensor, make_tensor, uniform_distinct, zipf_distinct, init_params,
-    epoch_perm, planted_values,
+    epoch_perm, planted_values, build,
 )
 from .configs import CONFIGS, Workload, get  # noqa: F401

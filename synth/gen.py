@@ -8,13 +8,48 @@ generators stand in for them with the shapes, value ranges and skewed
 Every function takes an explicit seed or numpy Generator, so both the oracle
 and the GPU library receive identical inputs.
 """
-from concurrent.futures import ThreadPoolExecutor
+import ctypes as C
+import os
+import subprocess
 from dataclasses import dataclass, field
 
 import numpy as np
-import pandas as pd
 
-_POOL = ThreadPoolExecutor(8)
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "_synth.c")
+_LIB = os.path.join(_HERE, "libsynth.so")
+_lib = None
+
+
+def build(force=False):
+    """Compile the generators' multi-threaded kernels (_synth.c) with gcc."""
+    if force or not os.path.exists(_LIB) or (
+            os.path.getmtime(_LIB) < os.path.getmtime(_SRC)):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared",
+                               "-fopenmp", "-ffp-contract=off", _SRC, "-o",
+                               tmp])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        build()
+        lib = C.CDLL(_LIB)
+        vp = C.c_void_p
+        lib.syn_zipf_lookup.argtypes = [vp, C.c_int64, vp, vp, C.c_int64, vp]
+        lib.syn_first_distinct.argtypes = [C.c_int, vp, C.c_int64, vp]
+        lib.syn_planted.argtypes = [C.c_int, C.c_int, vp, vp, C.c_int64,
+                                    C.c_double, vp]
+        lib.syn_planted.restype = None
+        _lib = lib
+    return _lib
+
+
+def _p(a):
+    return C.c_void_p(a.ctypes.data)
 
 
 def _rng(seed):
@@ -22,42 +57,16 @@ def _rng(seed):
         np.random.Generator(np.random.PCG64(seed))
 
 
-def _pack(idx, dims):
-    """Mixed-radix key of each coordinate tuple; exact in 128 bits, returned
-    as one uint64 when the key space fits, else as a structured pair."""
-    space = 1
-    for d in dims:
-        space *= int(d)
-    if space < 2 ** 63:
-        key = np.zeros(idx.shape[1], dtype=np.int64)
-        for n, d in enumerate(dims):
-            key = key * np.int64(d) + idx[n].astype(np.int64)
-        return key
-    # split the modes into two groups whose key spaces each fit in 63 bits
-    hi = np.zeros(idx.shape[1], dtype=np.int64)
-    lo = np.zeros(idx.shape[1], dtype=np.int64)
-    half = len(dims) // 2
-    for n, d in enumerate(dims):
-        if n < half:
-            hi = hi * np.int64(d) + idx[n].astype(np.int64)
-        else:
-            lo = lo * np.int64(d) + idx[n].astype(np.int64)
-    out = np.empty(idx.shape[1], dtype=[("hi", np.int64), ("lo", np.int64)])
-    out["hi"] = hi
-    out["lo"] = lo
-    return out
-
-
 def _first_distinct(idx, dims):
     """Indices of the first occurrence of every distinct tuple, in draw
-    order (hash-based duplicate detection)."""
-    key = _pack(idx, dims)
-    if key.dtype.names:
-        dup = pd.DataFrame({"hi": key["hi"], "lo": key["lo"]}).duplicated(
-            keep="first").values
-    else:
-        dup = pd.Series(key).duplicated(keep="first").values
-    return np.flatnonzero(~dup)
+    order (exact: hash buckets, full-tuple comparison)."""
+    idx = np.ascontiguousarray(idx, dtype=np.int32)
+    n = idx.shape[1]
+    keep = np.empty(n, dtype=np.uint8)
+    if n and _load().syn_first_distinct(idx.shape[0], _p(idx), n,
+                                        _p(keep)) != 0:
+        raise MemoryError("duplicate removal ran out of memory")
+    return np.flatnonzero(keep)
 
 
 def uniform_distinct(seed, dims, count):
@@ -89,12 +98,12 @@ class _Zipf:
 
     def draw(self, rng, size):
         u = rng.random(size)
-        parts = list(_POOL.map(
-            lambda c: np.searchsorted(self.cdf, c, side="right"),
-            np.array_split(u, 16)))
-        k = np.concatenate(parts)
-        np.minimum(k, len(self.cdf) - 1, out=k)
-        return self.label[k]
+        out = np.empty(size, dtype=np.int32)
+        if _load().syn_zipf_lookup(_p(self.cdf), len(self.cdf),
+                                   _p(self.label), _p(u), size,
+                                   _p(out)) != 0:
+            raise MemoryError("zipf lookup table")
+        return out
 
 
 def zipf_distinct(seed, dims, s, count, progress=None):
@@ -126,7 +135,7 @@ def zipf_distinct(seed, dims, s, count, progress=None):
 
 
 def planted_values(seed, dims, idx, J, R, a_std, b_std, scale=1.0,
-                   chunk=1 << 20, progress=None):
+                   progress=None):
     """Values of a planted low-rank tensor at the coordinates idx.
 
     Data synthesis only: draws planted matrices P^(n) (I_n x J) and
@@ -140,17 +149,14 @@ def planted_values(seed, dims, idx, J, R, a_std, b_std, scale=1.0,
     for d in dims:
         P = rng.normal(0.0, a_std, size=(int(d), J))
         Q = rng.normal(0.0, b_std, size=(J, R))
-        U.append((P @ Q).astype(np.float64))
+        U.append(np.ascontiguousarray(P @ Q, dtype=np.float64))
+    idx = np.ascontiguousarray(idx, dtype=np.int32)
     nnz = idx.shape[1]
     out = np.empty(nnz, dtype=np.float64)
-    for lo in range(0, nnz, chunk):
-        hi = min(nnz, lo + chunk)
-        prod = np.ones((hi - lo, R))
-        for n, u in enumerate(U):
-            prod *= u[idx[n, lo:hi]]
-        out[lo:hi] = prod.sum(axis=1) * scale
-        if progress and (hi // chunk) % 32 == 0:
-            progress(f"planted values {hi} of {nnz}")
+    up = (C.c_void_p * len(U))(*[u.ctypes.data for u in U])
+    _load().syn_planted(len(U), R, up, _p(idx), nnz, float(scale), _p(out))
+    if progress:
+        progress(f"planted values for {nnz} nonzeros")
     return out
 
 
@@ -205,9 +211,11 @@ def make_tensor(w, seed=None, cache_dir=None, progress=None):
         x = np.clip(np.rint(w.rating_offset + x), 1.0, 5.0)
     order = rng.permutation(w.nnz)
     n_test = int(round(w.nnz * w.test_frac))
-    te, tr = order[:n_test], order[n_test:]
-    te.sort()
-    tr.sort()
+    # the test set is order[:n_test]; both sets keep first-drawn order
+    in_test = np.zeros(w.nnz, dtype=bool)
+    in_test[order[:n_test]] = True
+    del order
+    te, tr = np.flatnonzero(in_test), np.flatnonzero(~in_test)
     return Tensor(dims=list(w.dims),
                   train_idx=np.ascontiguousarray(idx[:, tr]),
                   train_val=x[tr].astype(np.float32),

@@ -6,5 +6,5 @@ CPU-baseline leg use this package. It shares no code with the HIP library.
 from .oracle import (  # noqa: F401
     build, lib_path, use_library, predict, residual_stats, loss,
     factor_minibatch,
-    factor_epoch, core_grad, core_epoch,
+    factor_epoch, core_grad, core_epoch, set_threads,
 )

@@ -16,6 +16,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "ft_oracle.c")
+_SRC_PAR = os.path.join(_HERE, "ft_oracle_par.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
@@ -29,12 +30,15 @@ def lib_path():
 
 
 def build(force=False):
-    """Compile ft_oracle.c with gcc (strict IEEE: no fast-math)."""
+    """Compile ft_oracle.c with gcc (strict IEEE: no fast-math; OpenMP only
+    spreads the *_par functions' independent samples over threads)."""
     if force or not os.path.exists(_LIB) or (
-            os.path.getmtime(_LIB) < os.path.getmtime(_SRC)):
+            os.path.getmtime(_LIB) < max(os.path.getmtime(_SRC),
+                                         os.path.getmtime(_SRC_PAR))):
         tmp = _LIB + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared",
-                               "-ffp-contract=off", _SRC, "-o", tmp, "-lm"])
+                               "-fopenmp", "-ffp-contract=off", _SRC_PAR,
+                               "-o", tmp, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -80,6 +84,22 @@ def _load():
             C.c_int, _i64p, _i32p, C.c_int32, pp, pp, C.c_int64, _i32p, _dp,
             _i64p, C.c_int64, C.c_double, C.c_double, C.c_int]
         lib.orc_core_epoch.restype = C.c_double
+        if not hasattr(lib, "orc_factor_minibatch_par"):
+            _lib = lib       # a build of ft_oracle.c alone (mutant checks)
+            return _lib
+        lib.orc_factor_minibatch_par.argtypes = \
+            lib.orc_factor_minibatch.argtypes
+        lib.orc_factor_minibatch_par.restype = C.c_double
+        lib.orc_factor_epoch_par.argtypes = lib.orc_factor_epoch.argtypes
+        lib.orc_core_grad_par.argtypes = lib.orc_core_grad.argtypes
+        lib.orc_core_grad_par.restype = C.c_double
+        lib.orc_core_epoch_par.argtypes = [
+            C.c_int, _i32p, C.c_int32, pp, pp, C.c_int64, _i32p, _dp,
+            C.c_double, C.c_double]
+        lib.orc_core_epoch_par.restype = C.c_double
+        lib.orc_residual_stats_par.argtypes = lib.orc_residual_stats.argtypes
+        lib.orc_set_threads.argtypes = [C.c_int]
+        lib.orc_set_threads.restype = C.c_int
         _lib = lib
     return _lib
 
@@ -139,14 +159,22 @@ def predict(A, B, idx):
     return out
 
 
-def residual_stats(A, B, idx, vals):
-    """(sum (x - xhat)^2, sum |x - xhat|) over a set (Section 5.2 RMSE/MAE)."""
+def set_threads(n=0):
+    """Host threads of the parallel forms (n < 1: every core); returns the
+    count in force."""
+    return _load().orc_set_threads(int(n))
+
+
+def residual_stats(A, B, idx, vals, parallel=False):
+    """(sum (x - xhat)^2, sum |x - xhat|) over a set (Section 5.2 RMSE/MAE).
+    parallel: chunk sums over threads, added in chunk order."""
     lib = _load()
     N, dims, J, R = _shape(A, B)
     idx = _coords(idx, N, dims)
     vals = _vals(vals, idx.shape[1])
     sse, sae = C.c_double(), C.c_double()
-    lib.orc_residual_stats(N, J.ctypes.data_as(_i32p), R, _ptrs(A, "A"),
+    fn = lib.orc_residual_stats_par if parallel else lib.orc_residual_stats
+    fn(N, J.ctypes.data_as(_i32p), R, _ptrs(A, "A"),
                            _ptrs(B, "B"), idx.shape[1],
                            idx.ctypes.data_as(_i32p), vals.ctypes.data_as(_dp),
                            C.byref(sse), C.byref(sae))
@@ -166,11 +194,12 @@ def loss(A, B, idx, vals, lamA, lamB):
 
 
 def factor_minibatch(A, B, idx, vals, lrA, lamA, row_mean, apply=True,
-                     want_grad=False):
+                     want_grad=False, parallel=False):
     """One minibatch of Algorithm 3's factor loop, rule Eq. (12), Jacobi in
     the minibatch. Returns loss (sum r^2/2), and with want_grad the dense row
     gradients G[n] (I_n, J_n) (lamA * a included once per occurrence) and the
-    occurrence counts k[n] (I_n,)."""
+    occurrence counts k[n] (I_n,). parallel: per-sample work over threads,
+    bitwise the same results."""
     lib = _load()
     N, dims, J, R = _shape(A, B)
     idx = _coords(idx, N, dims)
@@ -182,7 +211,9 @@ def factor_minibatch(A, B, idx, vals, lrA, lamA, row_mean, apply=True,
         cnt = [np.zeros(dims[n], dtype=np.int64) for n in range(N)]
         gp = _ptrs(G, "G")
         cp = (_i64p * N)(*[c.ctypes.data_as(_i64p) for c in cnt])
-    l = lib.orc_factor_minibatch(
+    fn = lib.orc_factor_minibatch_par if parallel else \
+        lib.orc_factor_minibatch
+    l = fn(
         N, dims.ctypes.data_as(_i64p), J.ctypes.data_as(_i32p), R,
         _ptrs(A, "A"), _ptrs(B, "B"), idx.shape[1], idx.ctypes.data_as(_i32p),
         vals.ctypes.data_as(_dp), lrA, lamA, int(row_mean), int(apply), gp, cp)
@@ -191,9 +222,10 @@ def factor_minibatch(A, B, idx, vals, lrA, lamA, row_mean, apply=True,
     return l
 
 
-def factor_epoch(A, B, idx, vals, perm, M, lrA, lamA, row_mean):
+def factor_epoch(A, B, idx, vals, perm, M, lrA, lamA, row_mean,
+                 parallel=False):
     """Factor loop of Algorithm 3 over one permutation pass; returns the
-    per-minibatch losses (sum r^2/2)."""
+    per-minibatch losses (sum r^2/2). parallel: bitwise the same results."""
     lib = _load()
     N, dims, J, R = _shape(A, B)
     idx = _coords(idx, N, dims)
@@ -204,7 +236,8 @@ def factor_epoch(A, B, idx, vals, perm, M, lrA, lamA, row_mean):
         raise ValueError("perm must be (nnz,)")
     nmb = (nnz + M - 1) // M
     out = np.zeros(nmb)
-    lib.orc_factor_epoch(N, dims.ctypes.data_as(_i64p),
+    fn = lib.orc_factor_epoch_par if parallel else lib.orc_factor_epoch
+    fn(N, dims.ctypes.data_as(_i64p),
                          J.ctypes.data_as(_i32p), R, _ptrs(A, "A"),
                          _ptrs(B, "B"), nnz, idx.ctypes.data_as(_i32p),
                          vals.ctypes.data_as(_dp), perm.ctypes.data_as(_i64p),
@@ -212,14 +245,16 @@ def factor_epoch(A, B, idx, vals, perm, M, lrA, lamA, row_mean):
     return out
 
 
-def core_grad(A, B, idx, vals):
-    """Grad^(n) = sum r a^T d over a set (Algorithm 5 accumulation)."""
+def core_grad(A, B, idx, vals, parallel=False):
+    """Grad^(n) = sum r a^T d over a set (Algorithm 5 accumulation).
+    parallel: chunk sums over threads, added in chunk order."""
     lib = _load()
     N, dims, J, R = _shape(A, B)
     idx = _coords(idx, N, dims)
     vals = _vals(vals, idx.shape[1])
     Grad = [np.zeros((J[n], R)) for n in range(N)]
-    l = lib.orc_core_grad(N, J.ctypes.data_as(_i32p), R, _ptrs(A, "A"),
+    fn = lib.orc_core_grad_par if parallel else lib.orc_core_grad
+    l = fn(N, J.ctypes.data_as(_i32p), R, _ptrs(A, "A"),
                           _ptrs(B, "B"), idx.shape[1],
                           idx.ctypes.data_as(_i32p), vals.ctypes.data_as(_dp),
                           _ptrs(Grad, "Grad"))
@@ -227,14 +262,19 @@ def core_grad(A, B, idx, vals):
 
 
 def core_epoch(A, B, idx, vals, lrB, lamB, perm=None, M=0,
-               per_minibatch=False):
+               per_minibatch=False, parallel=False):
     """Algorithm 5 (one update per epoch) or, with per_minibatch, one update
-    per minibatch of the order perm. Returns sum r^2/2."""
+    per minibatch of the order perm. Returns sum r^2/2. parallel (Algorithm 5
+    only): the gradient's chunk sums over threads, added in chunk order."""
     lib = _load()
     N, dims, J, R = _shape(A, B)
     idx = _coords(idx, N, dims)
     nnz = idx.shape[1]
     vals = _vals(vals, nnz)
+    if parallel and not per_minibatch:
+        return lib.orc_core_epoch_par(
+            N, J.ctypes.data_as(_i32p), R, _ptrs(A, "A"), _ptrs(B, "B"), nnz,
+            idx.ctypes.data_as(_i32p), vals.ctypes.data_as(_dp), lrB, lamB)
     pp = None
     if per_minibatch:
         perm = np.ascontiguousarray(perm, dtype=np.int64)

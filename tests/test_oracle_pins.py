@@ -444,3 +444,43 @@ def test_core_epoch_per_minibatch_steps_with_tail(oracle_mod):
     assert lo == pytest.approx(lref, rel=1e-11)
     for n in range(3):
         np.testing.assert_allclose(Bo[n], Br[n], rtol=1e-11, atol=1e-13)
+
+
+@pytest.mark.parametrize("dims,J,R", [((9, 8, 7), (3, 4, 2), 5),
+                                      ((5, 4, 6, 3, 4, 5, 3), (2, 3, 2, 4, 2,
+                                                               3, 2), 3)])
+def test_parallel_forms_equal_the_serial_oracle(oracle_mod, dims, J, R):
+    """The all-core forms (timing only) give the serial loops' results: the
+    factor epoch bit for bit, the chunked core and residual sums to rounding
+    of the addition order."""
+    nnz = 9000
+    A, B, idx, vals = rand_problem(dims, J, R, nnz, 17)
+    perm = np.random.default_rng(3).permutation(nnz)
+    for threads in (1, 4):
+        oracle_mod.set_threads(threads)
+        for row_mean in (False, True):
+            A1 = [a.copy() for a in A]
+            A2 = [a.copy() for a in A]
+            l1 = oracle_mod.factor_epoch(A1, B, idx, vals, perm, 700, 0.05,
+                                         0.01, row_mean)
+            l2 = oracle_mod.factor_epoch(A2, B, idx, vals, perm, 700, 0.05,
+                                         0.01, row_mean, parallel=True)
+            np.testing.assert_array_equal(l1, l2)
+            for a1, a2 in zip(A1, A2):
+                np.testing.assert_array_equal(a1, a2)
+        l1, G1 = oracle_mod.core_grad(A, B, idx, vals)
+        l2, G2 = oracle_mod.core_grad(A, B, idx, vals, parallel=True)
+        assert l2 == pytest.approx(l1, rel=1e-13)
+        for g1, g2 in zip(G1, G2):
+            np.testing.assert_allclose(g2, g1, rtol=1e-12,
+                                       atol=1e-13 * np.abs(g1).max())
+        s1 = oracle_mod.residual_stats(A, B, idx, vals)
+        s2 = oracle_mod.residual_stats(A, B, idx, vals, parallel=True)
+        np.testing.assert_allclose(s2, s1, rtol=1e-13)
+        B1 = [b.copy() for b in B]
+        B2 = [b.copy() for b in B]
+        oracle_mod.core_epoch(A, B1, idx, vals, 0.3, 0.01)
+        oracle_mod.core_epoch(A, B2, idx, vals, 0.3, 0.01, parallel=True)
+        for b1, b2 in zip(B1, B2):
+            np.testing.assert_allclose(b2, b1, rtol=1e-12, atol=1e-14)
+    oracle_mod.set_threads(0)

@@ -18,8 +18,14 @@
  *   - Indices are 0-based int32; nonzero counts are int64.
  *   - All pointers in this header are HOST pointers unless the comment says
  *     "device". Input buffers are copied; the caller keeps ownership.
- *   - The device path supports order 2..5, 1 <= J_n <= 32 and 1 <= R <= 32
+ *   - The device path supports order 2..10, 1 <= J_n <= 32 and 1 <= R <= 32
  *     (zero padding of J and R to the matrix-core tile is exact for order >= 2).
+ *     Orders 2..5 run every option; orders 6..10 (the paper's high-order
+ *     synthetic tensors) run the FP32 verify path: ft_set_options rejects
+ *     BF16/FP8, the fast mode, vector_alu and core_storage there (FT_EINVAL);
+ *     their padded shape must satisfy order x J4 x R16 <= 6144 (J4 = max J_n
+ *     rounded up to 8, 16 or 32; R16 = R rounded up to 16), e.g. every order
+ *     at J = R = 16 and order 6 at J = R = 32.
  */
 #ifndef FT_H
 #define FT_H
@@ -90,6 +96,16 @@ typedef struct {
                                   matrix-core ablation; FP32 and the verify
                                   mode only (FT_EINVAL otherwise); the
                                   stateless ft_mb_* calls ignore it         */
+    int32_t core_storage;      /* core phase, storage against calculation
+                                  (the paper's comparison of the two):
+                                  0: every sample contracts its rows of A
+                                  with B on the matrix cores (calculation);
+                                  1: each core pass first stores C^(n) =
+                                  A^(n) B^(n) for every row (I_n x R, FP32,
+                                  kept by the handle) and the samples gather
+                                  rows of C instead; FP32, the verify mode
+                                  and vector_alu = 0 only (FT_EINVAL
+                                  otherwise). Same results up to rounding. */
 } ft_options;
 
 /* Kernel classes that ft_profile_get reports. */
@@ -104,7 +120,8 @@ typedef enum {
     FT_K_CORE_UPDATE = 7,  /* fixed-order partial sum + core update          */
     FT_K_EVAL = 8,         /* forward-only residual statistics               */
     FT_K_HOGWILD = 9,      /* fast-mode factor sweep                         */
-    FT_K_COUNT = 10
+    FT_K_PRECOMPUTE_C = 10,/* stored C = A B of the storage variant          */
+    FT_K_COUNT = 11
 } ft_kernel;
 
 /* Fill *o with the defaults: M = 512, lr 0.01, lambda 1e-3, FP32, ROW_SUM,
@@ -233,9 +250,9 @@ ft_status ft_profile_get(ft_handle *h, int32_t kernel, int64_t *launches,
  *   val    device FP32, m values
  * ------------------------------------------------------------------------ */
 typedef struct {
-    int32_t order;       /* 2..5                                            */
-    int64_t dims[5];     /* I_n                                             */
-    int32_t J[5];        /* 1..32                                           */
+    int32_t order;       /* 2..10 (FP32 kernels above 5)                     */
+    int64_t dims[10];    /* I_n (the first `order` entries are read)        */
+    int32_t J[10];       /* 1..32                                           */
     int32_t R;           /* 1..32                                           */
 } ft_problem_desc;
 

@@ -17,7 +17,8 @@ FT_FP32, FT_BF16, FT_FP8_E4M3 = 0, 1, 2
 FT_ROW_SUM, FT_ROW_MEAN = 0, 1
 FT_CORE_PER_EPOCH, FT_CORE_PER_MINIBATCH = 0, 1
 KERNELS = ["order", "permute", "sort", "factor_grad", "seg_reduce",
-           "seg_combine", "core_grad", "core_update", "eval", "hogwild"]
+           "seg_combine", "core_grad", "core_update", "eval", "hogwild",
+           "precompute_c"]
 
 
 class Options(C.Structure):
@@ -27,12 +28,12 @@ class Options(C.Structure):
                 ("row_scale", C.c_int32), ("core_step", C.c_int32),
                 ("deterministic", C.c_int32), ("shuffle_seed", C.c_uint64),
                 ("reshuffle_each_epoch", C.c_int32),
-                ("vector_alu", C.c_int32)]
+                ("vector_alu", C.c_int32), ("core_storage", C.c_int32)]
 
 
 class ProblemDesc(C.Structure):
-    _fields_ = [("order", C.c_int32), ("dims", C.c_int64 * 5),
-                ("J", C.c_int32 * 5), ("R", C.c_int32)]
+    _fields_ = [("order", C.c_int32), ("dims", C.c_int64 * 10),
+                ("J", C.c_int32 * 10), ("R", C.c_int32)]
 
 
 _H = C.c_void_p

@@ -8,8 +8,9 @@ deterministic sorted reduction (sparse rows or a dense matrix) and the core
 gradients are reduced in a fixed order. torch provides device memory and the
 stream only.
 
-Layout: A[n] is (I_n, J4) float32 with J4 = max J_n rounded up to 4 and zero
-columns beyond J_n (FastTuckerModel keeps it so); B[n] is (J_n, R) float32.
+Layout: A[n] is (I_n, J4) float32 with J4 = max J_n rounded up to 4 (to 8,
+16 or 32 above order 5) and zero columns beyond J_n (FastTuckerModel keeps it
+so); B[n] is (J_n, R) float32.
 """
 import ctypes as C
 
@@ -26,7 +27,12 @@ def _check(status):
 
 
 def j4_of(J):
-    return (max(J) + 3) // 4 * 4
+    """Row stride of A: max J_n rounded up to 4 (orders up to 5), or to 8,
+    16 or 32 (orders 6..10), as the library pads it."""
+    j4 = (max(J) + 3) // 4 * 4
+    if len(J) <= 5:
+        return j4
+    return 8 if j4 <= 8 else 16 if j4 <= 16 else 32
 
 
 def _desc(dims, J, R):

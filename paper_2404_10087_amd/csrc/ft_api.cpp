@@ -42,7 +42,8 @@ struct EpochBufs {
     uint32_t *inv[kMaxOrder] = {};    // sorted index of every position
     uint32_t *counts = nullptr;
     size_t counts_cap = 0;
-    int sort_final = 0;
+    int sort_final[kMaxOrder] = {};   // ping-pong set holding each mode's
+                                      // sorted rows
     int4 *xlist = nullptr;            // crossing rows per minibatch and mode
     size_t xlist_cap = 0;
     int4 *plist = nullptr;            // their parts of kPartRows samples
@@ -108,6 +109,7 @@ struct ft_handle {
     size_t tile_loss_cap = 0;
 
     // core-phase / evaluation scratch
+    float *Cst[kMaxOrder] = {};       // stored C^(n) (core_storage)
     float *core_part = nullptr;
     size_t core_part_cap = 0;
     double *dpart = nullptr;
@@ -301,6 +303,7 @@ static void release(ft_handle *h) {
         dfree(h->A16[n]);
         dfree(h->A8[n]);
         dfree(h->As[n]);
+        dfree(h->Cst[n]);
 
         for (int s = 0; s < 2; ++s) dfree(h->idx[s][n]);
     }
@@ -340,6 +343,7 @@ extern "C" ft_status ft_default_options(ft_options *o) {
     o->shuffle_seed = 0;
     o->reshuffle_each_epoch = 1;
     o->vector_alu = 0;
+    o->core_storage = 0;
     return FT_OK;
 }
 
@@ -389,6 +393,20 @@ static ft_status check_options(ft_handle *h, const ft_options *o) {
          !factor_valu_supported(vsh)))
         return fail(h, FT_EINVAL,
                     "vector_alu needs FP32 and the verify mode");
+    if (o->core_storage != 0 && o->core_storage != 1)
+        return fail(h, FT_EINVAL, "core_storage must be 0 or 1");
+    if (h->N > kFullOrder &&
+        (o->precision != FT_FP32 || !o->deterministic || o->vector_alu ||
+         o->core_storage))
+        return fail(h, FT_EINVAL,
+                    "orders above %d run the FP32 verify path only (no "
+                    "BF16/FP8, fast mode, vector_alu or core_storage)",
+                    kFullOrder);
+    if (o->core_storage &&
+        (o->precision != FT_FP32 || !o->deterministic || o->vector_alu))
+        return fail(h, FT_EINVAL,
+                    "core_storage needs FP32, the verify mode and "
+                    "vector_alu = 0");
     return FT_OK;
 }
 
@@ -473,6 +491,16 @@ extern "C" ft_status ft_create(int order, const int64_t *dims,
     }
     if (R < 1 || R > kMaxR)
         return fail(nullptr, FT_EINVAL, "R = %d out of [1, %d]", R, kMaxR);
+    {
+        int jmax = 0;
+        for (int n = 0; n < order; ++n) jmax = std::max(jmax, (int)J[n]);
+        if (!high_order_fits(order, padded_j4(order, jmax), (R + 15) / 16 * 16))
+            return fail(nullptr, FT_EINVAL,
+                        "order %d with J4 = %d and R16 = %d exceeds the core "
+                        "kernel's LDS (order x J4 x R16 <= %d above order %d)",
+                        order, padded_j4(order, jmax), (R + 15) / 16 * 16,
+                        kHighOrderTile, kFullOrder);
+    }
 
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1)
@@ -493,7 +521,7 @@ extern "C" ft_status ft_create(int order, const int64_t *dims,
     }
     h->R = R;
     h->sh.N = order;
-    h->sh.J4 = (jmax + 3) / 4 * 4;
+    h->sh.J4 = padded_j4(order, jmax);
     h->sh.R16 = (R + 15) / 16 * 16;
     ft_default_options(&h->opt);
 
@@ -703,12 +731,6 @@ static ft_status build_minibatches(ft_handle *h, EpochBufs &E, hipStream_t s,
     const int64_t M = h->opt.minibatch;
     const int nseg = (int)nminibatches(h);
     const int tps = (int)((std::min<int64_t>(M, nnz) + kSortTile - 1) / kSortTile);
-    int64_t maxrow = 0;
-    for (int n = 0; n < h->N; ++n)
-        if (h->dims[n] - 1 > maxrow) maxrow = h->dims[n] - 1;
-    int bits = 0;
-    while ((1ll << bits) <= maxrow) ++bits;
-    const int passes = bits == 0 ? 1 : (bits + 7) / 8;
     const size_t nx = (size_t)nseg * h->N * kXCounts;
     HIPCHK(h, ensure(&E.counts, &E.counts_cap,
                      (size_t)h->N * nseg * kRadix * tps));
@@ -734,32 +756,41 @@ static ft_status build_minibatches(ft_handle *h, EpochBufs &E, hipStream_t s,
     p.tiles_per_seg = tps;
     p.counts = E.counts;
     p.grid_cap = cap;
-    int cur = 0;
-    for (int pass = 0; pass < passes; ++pass) {
+    // each mode takes as many 8-bit passes as its own row ids need; a pass
+    // sorts the modes that still have digits left (packed into slots)
+    int passes[kMaxOrder], cur[kMaxOrder] = {}, max_passes = 1;
+    for (int n = 0; n < h->N; ++n) {
+        passes[n] = radix_passes(h->dims[n]);
+        max_passes = std::max(max_passes, passes[n]);
+    }
+    for (int pass = 0; pass < max_passes; ++pass) {
         p.shift = 8 * pass;
+        p.N = 0;
         for (int n = 0; n < h->N; ++n) {
-            p.key_in[n] = pass == 0 ? reinterpret_cast<const uint32_t *>(E.pidx[n])
-                                    : E.sk[cur][n];
-            p.val_in[n] = pass == 0 ? nullptr : E.sv[cur][n];
-            p.key_out[n] = E.sk[pass == 0 ? 0 : cur ^ 1][n];
+            if (pass >= passes[n]) continue;
+            const int k = p.N++;
+            const int out = pass == 0 ? 0 : cur[n] ^ 1;
+            const bool last = pass == passes[n] - 1;
+            p.key_in[k] = pass == 0 ? reinterpret_cast<const uint32_t *>(E.pidx[n])
+                                    : E.sk[cur[n]][n];
+            p.val_in[k] = pass == 0 ? nullptr : E.sv[cur[n]][n];
+            p.key_out[k] = E.sk[out][n];
             // the last pass keeps the sorted rows and the inverse; the
             // sorted positions themselves are not needed downstream
-            p.val_out[n] = pass == passes - 1
-                               ? nullptr
-                               : E.sv[pass == 0 ? 0 : cur ^ 1][n];
-            p.inv_out[n] = pass == passes - 1 ? E.inv[n] : nullptr;
+            p.val_out[k] = last ? nullptr : E.sv[out][n];
+            p.inv_out[k] = last ? E.inv[n] : nullptr;
+            cur[n] = out;
         }
-        cur = pass == 0 ? 0 : cur ^ 1;
         HIPCHK(h, launch_sort_pass(p, s));
     }
-    E.sort_final = cur;
+    for (int n = 0; n < h->N; ++n) E.sort_final[n] = cur[n];
     CrossArgs cx{};
     cx.N = h->N;
     cx.nnz = nnz;
     cx.M = M;
     cx.nseg = nseg;
     cx.xcap = xcap;
-    for (int n = 0; n < h->N; ++n) cx.rows[n] = E.sk[cur][n];
+    for (int n = 0; n < h->N; ++n) cx.rows[n] = E.sk[cur[n]][n];
     cx.xlist = E.xlist;
     cx.plist = E.plist;
     cx.pcap = pcap;
@@ -893,7 +924,7 @@ static ft_status run_minibatch(ft_handle *h, int64_t b, int apply,
     sa.m = m;
     sa.nchunks = (m + kSegChunk - 1) / kSegChunk;
     for (int n = 0; n < h->N; ++n) {
-        sa.rows[n] = E.sk[E.sort_final][n] + off;
+        sa.rows[n] = E.sk[E.sort_final[n]][n] + off;
         sa.A[n] = h->A[n];
         sa.A16[n] = h->sh.prec == kBF16 ? h->A16[n] : nullptr;
         sa.A8[n] = h->sh.prec == kFP8 ? h->A8[n] : nullptr;
@@ -1131,10 +1162,24 @@ static ft_status core_pass(ft_handle *h, const int32_t *const *idx,
     ca.loss_part = h->dpart;
     int used = nb;
     ca.blocks_used = &used;
+    if (h->opt.core_storage) {
+        // A and B are fixed for the pass: store every row's C = a B once
+        for (int n = 0; n < h->N; ++n) {
+            if (!h->Cst[n])
+                HIPCHK(h, hipMalloc(&h->Cst[n], sizeof(float) * h->dims[n] *
+                                                    h->sh.R16));
+            LaunchExt L(h, FT_K_PRECOMPUTE_C);
+            HIPCHK(h, launch_precompute_c(h->sh, h->A[n], h->B[n], h->dims[n],
+                                          h->Cst[n], h->stream));
+            ca.Cst[n] = h->Cst[n];
+        }
+    }
     {
         LaunchExt L(h, FT_K_CORE_GRAD);
         if (h->opt.vector_alu)
             HIPCHK(h, launch_core_grad_valu(h->sh, ca, nb, h->stream));
+        else if (h->opt.core_storage)
+            HIPCHK(h, launch_core_grad_stored(h->sh, ca, nb, h->stream));
         else
             HIPCHK(h, launch_core_grad(h->sh, ca, nb, h->stream));
     }
@@ -1355,7 +1400,7 @@ extern "C" ft_status ft_get_minibatch_sort(ft_handle *h, int64_t b, int mode,
     HIPCHK(h, hipMemcpyAsync(inv.data(), E.inv[mode] + off,
                              sizeof(uint32_t) * m, hipMemcpyDeviceToHost,
                              h->stream));
-    HIPCHK(h, hipMemcpyAsync(rows, E.sk[E.sort_final][mode] + off,
+    HIPCHK(h, hipMemcpyAsync(rows, E.sk[E.sort_final[mode]][mode] + off,
                              sizeof(int32_t) * m, hipMemcpyDeviceToHost,
                              h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
@@ -1422,6 +1467,15 @@ ft_status check_desc(const ft_problem_desc *p, int64_t m) {
     }
     if (p->R < 1 || p->R > kMaxR)
         return fail(nullptr, FT_EINVAL, "R out of [1, %d]", kMaxR);
+    {
+        int jmax = 0;
+        for (int n = 0; n < p->order; ++n) jmax = std::max(jmax, (int)p->J[n]);
+        if (!high_order_fits(p->order, padded_j4(p->order, jmax),
+                             (p->R + 15) / 16 * 16))
+            return fail(nullptr, FT_EINVAL,
+                        "order %d: order x J4 x R16 exceeds %d", p->order,
+                        kHighOrderTile);
+    }
     if (m < 1 || m > (1ll << 30))
         return fail(nullptr, FT_EINVAL, "m must be in [1, 2^30], got %lld",
                     (long long)m);
@@ -1433,7 +1487,7 @@ MbLayout mb_layout(const ft_problem_desc *p, int64_t m) {
     int jmax = 0;
     for (int n = 0; n < p->order; ++n) jmax = std::max(jmax, (int)p->J[n]);
     L.sh.N = p->order;
-    L.sh.J4 = (jmax + 3) / 4 * 4;
+    L.sh.J4 = padded_j4(p->order, jmax);
     L.sh.R16 = (p->R + 15) / 16 * 16;
     const size_t N = (size_t)p->order, J4 = L.sh.J4, R16 = L.sh.R16;
     L.tps = (int)((m + kSortTile - 1) / kSortTile);
@@ -1629,26 +1683,28 @@ static ft_status mb_backward_run(
                        at<uint32_t>(workspace, L.sk1)};
     uint32_t *sv[2] = {at<uint32_t>(workspace, L.sv0),
                        at<uint32_t>(workspace, L.sv1)};
-    int64_t maxrow = 0;
-    for (int n = 0; n < N; ++n) maxrow = std::max<int64_t>(maxrow, p->dims[n] - 1);
-    int bits = 0;
-    while ((1ll << bits) <= maxrow) ++bits;
-    const int passes = bits == 0 ? 1 : (bits + 7) / 8;
-    int cur = 0;
-    for (int pass = 0; pass < passes; ++pass) {
+    int passes[kMaxOrder], cur[kMaxOrder] = {}, max_passes = 1;
+    for (int n = 0; n < N; ++n) {
+        passes[n] = radix_passes(p->dims[n]);
+        max_passes = std::max(max_passes, passes[n]);
+    }
+    for (int pass = 0; pass < max_passes; ++pass) {
         sp.shift = 8 * pass;
-        const int out = pass == 0 ? 0 : cur ^ 1;
+        sp.N = 0;
         for (int n = 0; n < N; ++n) {
-            sp.key_in[n] = pass == 0 ? reinterpret_cast<const uint32_t *>(idx[n])
-                                     : sk[cur] + (size_t)n * m;
-            sp.val_in[n] = pass == 0 ? nullptr : sv[cur] + (size_t)n * m;
-            sp.key_out[n] = sk[out] + (size_t)n * m;
-            sp.val_out[n] =
-                pass == passes - 1 ? nullptr : sv[out] + (size_t)n * m;
-            sp.inv_out[n] = pass == passes - 1 ? inv + (size_t)n * m : nullptr;
+            if (pass >= passes[n]) continue;
+            const int k = sp.N++;
+            const int out = pass == 0 ? 0 : cur[n] ^ 1;
+            const bool last = pass == passes[n] - 1;
+            sp.key_in[k] = pass == 0 ? reinterpret_cast<const uint32_t *>(idx[n])
+                                     : sk[cur[n]] + (size_t)n * m;
+            sp.val_in[k] = pass == 0 ? nullptr : sv[cur[n]] + (size_t)n * m;
+            sp.key_out[k] = sk[out] + (size_t)n * m;
+            sp.val_out[k] = last ? nullptr : sv[out] + (size_t)n * m;
+            sp.inv_out[k] = last ? inv + (size_t)n * m : nullptr;
+            cur[n] = out;
         }
         HIPCHK0(launch_sort_pass(sp, s));
-        cur = out;
     }
     int nb = 0;
     HIPCHK0(launch_factor_grad(L.sh, fa, &nb, s));
@@ -1668,7 +1724,7 @@ static ft_status mb_backward_run(
         cx.M = m;
         cx.nseg = 1;
         cx.xcap = L.xcap;
-        for (int n = 0; n < N; ++n) cx.rows[n] = sk[cur] + (size_t)n * m;
+        for (int n = 0; n < N; ++n) cx.rows[n] = sk[cur[n]] + (size_t)n * m;
         cx.xlist = at<int4>(workspace, L.xlist);
         cx.plist = at<int4>(workspace, L.plist);
         cx.pcap = L.pcap;
@@ -1690,7 +1746,7 @@ static ft_status mb_backward_run(
         }
     }
     for (int n = 0; n < N; ++n) {
-        sa.rows[n] = sk[cur] + (size_t)n * m;
+        sa.rows[n] = sk[cur[n]] + (size_t)n * m;
         sa.A[n] = const_cast<float *>(A[n]);
         sa.grad[n] = gradA ? gradA[n] : nullptr;
         if (gradA)

@@ -28,7 +28,11 @@ extern thread_local ExtEvents g_ext_events;
         }                                                                     \
     } while (0)
 
-constexpr int kMaxOrder = 5;
+constexpr int kMaxOrder = 10;
+// Orders up to kFullOrder run every variant (precisions, fast mode, vector
+// ALU, stored C) at every padded J4 in 4..32; higher orders run the FP32
+// verify path with J4 padded to 8, 16 or 32 (fewer kernel instances).
+constexpr int kFullOrder = 5;
 constexpr int kMaxJ = 32;
 constexpr int kMaxR = 32;
 
@@ -77,7 +81,20 @@ hipError_t launch_epoch_order(uint32_t *perm, int64_t n, uint64_t key,
 hipError_t launch_copy_order(uint32_t *perm, const int64_t *src, int64_t n,
                              hipStream_t s);
 // Training-set records: RW = 4 words (order <= 3) or 8 words (order 4..5).
-inline int record_words(int N) { return N <= 3 ? 4 : 8; }
+inline int record_words(int N) { return N <= 3 ? 4 : N <= 7 ? 8 : 16; }
+// Row stride of A^(n) (and rows of B^(n)): max J_n rounded up to 4, or for
+// orders above kFullOrder to 8, 16 or 32. Zero padding is exact.
+// Above kFullOrder the core kernel's four per-wave partials (4 x N x J4 x
+// R16 floats) and B-operands must fit in one block's 160 KB of LDS.
+constexpr int kHighOrderTile = 6144;
+inline bool high_order_fits(int N, int J4, int R16) {
+    return N <= kFullOrder || N * J4 * R16 <= kHighOrderTile;
+}
+inline int padded_j4(int N, int jmax) {
+    const int j4 = (jmax + 3) / 4 * 4;
+    if (N <= kFullOrder) return j4;
+    return j4 <= 8 ? 8 : j4 <= 16 ? 16 : 32;
+}
 hipError_t launch_pack_records(int N, const int32_t *const *idx,
                                const float *val, int64_t nnz, uint32_t *rec,
                                int rw, hipStream_t s);
@@ -87,7 +104,7 @@ hipError_t launch_permute(int N, const uint32_t *rec, int rw,
                           int grid_cap = 0);
 
 struct SortPass {
-    int N;
+    int N;               // modes sorted by this pass (slots 0 .. N-1)
     int64_t nnz;
     int64_t M;           // segment (minibatch) length
     int nseg;
@@ -103,6 +120,12 @@ struct SortPass {
     int grid_cap;        // > 0: at most this many workgroups (background)
 };
 hipError_t launch_sort_pass(const SortPass &p, hipStream_t s);
+// 8-bit LSD passes that sort row ids 0 .. dims - 1 (at least one)
+inline int radix_passes(int64_t dims) {
+    int bits = 0;
+    while ((1ll << bits) <= dims - 1) ++bits;
+    return bits == 0 ? 1 : (bits + 7) / 8;
+}
 
 // ---------------------------------------------------------------- factor phase
 struct FactorArgs {
@@ -236,12 +259,20 @@ struct CoreArgs {
     float *part;          // [nblocks][N][J4][R16]
     double *loss_part;    // [nblocks]
     int *blocks_used;     // host: the grid actually launched
+    const float *Cst[kMaxOrder];  // stored C^(n) = A^(n) B^(n), I_n x R16
+                                  // (core_grad_stored_kernel only)
 };
 // Upper bound of the core-gradient grid (partial buffers are sized for it);
 // the launch may use fewer blocks (what fits on the device at once).
 int core_grad_blocks(int64_t count);
 hipError_t launch_core_grad(const Shape &sh, const CoreArgs &a, int nblocks,
                             hipStream_t s);
+// Storage variant: C^(n) = A^(n) B^(n) formed once per pass into Cst
+// (rows x R16), then the same partials from gathered rows of C and A (FP32).
+hipError_t launch_precompute_c(const Shape &sh, const float *A, const float *B,
+                               int64_t rows, float *Cst, hipStream_t s);
+hipError_t launch_core_grad_stored(const Shape &sh, const CoreArgs &a,
+                                   int nblocks, hipStream_t s);
 // The same partials from vector FP32 FMAs (FP32 only; the ablation of the
 // matrix cores). The grid is capped by residency and by the chunk count.
 hipError_t launch_core_grad_valu(const Shape &sh, const CoreArgs &a,

@@ -112,8 +112,9 @@ hipError_t launch_copy_order(uint32_t *perm, const int64_t *src, int64_t n,
 
 // ------------------------------------------------------------------ permute
 // The training set is also kept as records (i_1..i_N, x) of RW 32-bit words
-// (RW = 4 for order <= 3, 8 otherwise), so the random gather of one sample is
-// one 16- or 32-byte load: pidx[n][p] = rec[perm[p]].i_n, pval[p] = .x.
+// (RW = 4 for order <= 3, 8 up to order 7, 16 above), so the random gather of
+// one sample is one 16-, 32- or 64-byte load: pidx[n][p] = rec[perm[p]].i_n,
+// pval[p] = .x.
 hipError_t launch_pack_records(int N, const int32_t *const *idx,
                                const float *val, int64_t nnz, uint32_t *rec,
                                int rw, hipStream_t s);
@@ -156,9 +157,12 @@ hipError_t launch_pack_records(int N, const int32_t *const *idx,
     if (rw == 4)
         hipLaunchKernelGGL(pack_records_kernel<4>, dim3(blocks), dim3(256), 0,
                            s, a);
-    else
+    else if (rw == 8)
         hipLaunchKernelGGL(pack_records_kernel<8>, dim3(blocks), dim3(256), 0,
                            s, a);
+    else
+        hipLaunchKernelGGL(pack_records_kernel<16>, dim3(blocks), dim3(256),
+                           0, s, a);
     return hipGetLastError();
 }
 
@@ -187,8 +191,9 @@ __global__ void permute_kernel(PermuteArgs a) {
             w[k + 2] = v.z;
             w[k + 3] = v.w;
         }
+        constexpr int NW = RW - 1 < kMaxOrder ? RW - 1 : kMaxOrder;
 #pragma unroll
-        for (int n = 0; n < kMaxOrder; ++n)
+        for (int n = 0; n < NW; ++n)
             if (n < a.N) a.pidx[n][p] = (int32_t)w[n];
         a.pval[p] = __uint_as_float(w[RW - 1]);
     }
@@ -209,8 +214,11 @@ hipError_t launch_permute(int N, const uint32_t *rec, int rw,
     if (grid_cap > 0 && blocks > grid_cap) blocks = grid_cap;
     if (rw == 4)
         hipLaunchKernelGGL(permute_kernel<4>, dim3(blocks), dim3(256), 0, s, a);
-    else
+    else if (rw == 8)
         hipLaunchKernelGGL(permute_kernel<8>, dim3(blocks), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL(permute_kernel<16>, dim3(blocks), dim3(256), 0, s,
+                           a);
     return hipGetLastError();
 }
 

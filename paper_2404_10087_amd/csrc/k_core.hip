@@ -65,6 +65,8 @@ __device__ __forceinline__ void load_core_tile(const CoreArgs &a, int64_t tile,
 // in 128 registers without spilling (checked per shape at build time), else
 // the compiler's choice.
 constexpr int core_waves(int N, int KQ, int RB, int P) {
+    if (N > kFullOrder)   // high orders: one wave per SIMD keeps the tile
+        return 1;         // in registers (orders 9-10 at J = R = 32 spill)
     if (N * RB * KQ > 32)   // B-operands in LDS: two waves fit, except
         return (P == kF32 && N == 5 && KQ * RB >= 14) ? 1 : 2;  // (spills)
     if (P == kFP8)   // the scale shuffles need a few more registers
@@ -294,28 +296,42 @@ static hipError_t launch_cg_p(const Shape &sh, const CoreArgs &a, int blocks,
 template <int N, int KQ>
 static hipError_t launch_cg_r(const Shape &sh, const CoreArgs &a, int blocks,
                               hipStream_t s) {
-    switch (sh.prec) {
-    case kF32: return launch_cg_p<N, KQ, kF32>(sh, a, blocks, s);
-    case kBF16: return launch_cg_p<N, KQ, kBF16>(sh, a, blocks, s);
-    case kFP8: return launch_cg_p<N, KQ, kFP8>(sh, a, blocks, s);
+    if constexpr (N > kFullOrder) {  // FP32 only above the full orders
+        return sh.prec == kF32 ? launch_cg_p<N, KQ, kF32>(sh, a, blocks, s)
+                               : hipErrorInvalidValue;
+    } else {
+        switch (sh.prec) {
+        case kF32: return launch_cg_p<N, KQ, kF32>(sh, a, blocks, s);
+        case kBF16: return launch_cg_p<N, KQ, kBF16>(sh, a, blocks, s);
+        case kFP8: return launch_cg_p<N, KQ, kFP8>(sh, a, blocks, s);
+        }
+        return hipErrorInvalidValue;
     }
-    return hipErrorInvalidValue;
 }
 
 template <int N>
 static hipError_t launch_cg_j(const Shape &sh, const CoreArgs &a, int blocks,
                               hipStream_t s) {
-    switch (sh.J4) {
-    case 4: return launch_cg_r<N, 1>(sh, a, blocks, s);
-    case 8: return launch_cg_r<N, 2>(sh, a, blocks, s);
-    case 12: return launch_cg_r<N, 3>(sh, a, blocks, s);
-    case 16: return launch_cg_r<N, 4>(sh, a, blocks, s);
-    case 20: return launch_cg_r<N, 5>(sh, a, blocks, s);
-    case 24: return launch_cg_r<N, 6>(sh, a, blocks, s);
-    case 28: return launch_cg_r<N, 7>(sh, a, blocks, s);
-    case 32: return launch_cg_r<N, 8>(sh, a, blocks, s);
+    if constexpr (N > kFullOrder) {   // J4 padded to 8, 16 or 32
+        switch (sh.J4) {
+        case 8: return launch_cg_r<N, 2>(sh, a, blocks, s);
+        case 16: return launch_cg_r<N, 4>(sh, a, blocks, s);
+        case 32: return launch_cg_r<N, 8>(sh, a, blocks, s);
+        }
+        return hipErrorInvalidValue;
+    } else {
+        switch (sh.J4) {
+        case 4: return launch_cg_r<N, 1>(sh, a, blocks, s);
+        case 8: return launch_cg_r<N, 2>(sh, a, blocks, s);
+        case 12: return launch_cg_r<N, 3>(sh, a, blocks, s);
+        case 16: return launch_cg_r<N, 4>(sh, a, blocks, s);
+        case 20: return launch_cg_r<N, 5>(sh, a, blocks, s);
+        case 24: return launch_cg_r<N, 6>(sh, a, blocks, s);
+        case 28: return launch_cg_r<N, 7>(sh, a, blocks, s);
+        case 32: return launch_cg_r<N, 8>(sh, a, blocks, s);
+        }
+        return hipErrorInvalidValue;
     }
-    return hipErrorInvalidValue;
 }
 
 hipError_t launch_core_grad(const Shape &sh, const CoreArgs &a, int nblocks,
@@ -326,6 +342,282 @@ hipError_t launch_core_grad(const Shape &sh, const CoreArgs &a, int nblocks,
     case 3: return launch_cg_j<3>(sh, a, nblocks, s);
     case 4: return launch_cg_j<4>(sh, a, nblocks, s);
     case 5: return launch_cg_j<5>(sh, a, nblocks, s);
+    case 6: return launch_cg_j<6>(sh, a, nblocks, s);
+    case 7: return launch_cg_j<7>(sh, a, nblocks, s);
+    case 8: return launch_cg_j<8>(sh, a, nblocks, s);
+    case 9: return launch_cg_j<9>(sh, a, nblocks, s);
+    case 10: return launch_cg_j<10>(sh, a, nblocks, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+// ------------------------------------------------- stored-C core kernel
+// The storage variant of the core phase (the paper's storage-against-
+// calculation comparison): with A and B fixed for the whole pass, every row's
+// C^(n)_i = a^(n)_i B^(n) is formed once (precompute_c_kernel) and the core
+// kernel gathers the R-wide rows of C instead of contracting the J-wide rows
+// of A with B; it still gathers the rows of A for E^(n) = r (*) A_Psi^(n).
+// FP32 only. The tile, transpose and accumulation are those of
+// core_grad_kernel, so the two give the same partials up to the rounding of
+// C (the stored C is the same FP32 product, summed in order over j).
+
+// C^(n) (rows x R16, row-major) <- A^(n) (rows x J4) B^(n) (J4 x R16): one
+// thread per four consecutive entries of a row, B staged in LDS.
+template <int J4, int R16>
+__global__ __launch_bounds__(256) void precompute_c_kernel(const float *A,
+                                                           const float *B,
+                                                           int64_t rows,
+                                                           float *Cst) {
+    __shared__ float sB[J4 * R16];
+    for (int e = threadIdx.x; e < J4 * R16; e += 256) sB[e] = B[e];
+    __syncthreads();
+    constexpr int QR = R16 / 4;
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t row = t / QR;
+    const int rq = (int)(t % QR);
+    if (row >= rows) return;
+    const float4 *a4 = reinterpret_cast<const float4 *>(A + row * J4);
+    float acc[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int jq = 0; jq < J4 / 4; ++jq) {
+        const float4 av = a4[jq];
+        const float aj[4] = {av.x, av.y, av.z, av.w};
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                acc[k] = fmaf(aj[e], sB[(4 * jq + e) * R16 + 4 * rq + k],
+                              acc[k]);
+    }
+    reinterpret_cast<float4 *>(Cst + row * R16)[rq] =
+        make_float4(acc[0], acc[1], acc[2], acc[3]);
+}
+
+template <int N, int KQ, int RB>
+struct StoredTileIn {
+    RowFrag<KQ, kF32> arow[N];   // A[s = c][KQ q .. KQ q + KQ - 1]
+    floatx4 C[N][RB];            // C[s = 4q + v][r = 16 rb + c]
+    float x[4];                  // values of samples 4q + v
+};
+
+template <int N, int KQ, int RB>
+__device__ __forceinline__ void load_stored_tile(const CoreArgs &a,
+                                                 int64_t tile, int q, int c,
+                                                 StoredTileIn<N, KQ, RB> &in) {
+    constexpr int J4 = 4 * KQ;
+    constexpr int R16 = 16 * RB;
+    const int64_t base = tile * 16;
+    const int64_t last = a.count - 1;
+    const int64_t ps = base + c <= last ? base + c : last;
+#pragma unroll
+    for (int n = 0; n < N; ++n) {
+        const int row = a.idx[n][ps];
+        in.arow[n].load(RowSrc{a.A[n], nullptr, nullptr, nullptr}, row, J4, q);
+        // rows of samples 4q + v come from the lanes that loaded them
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int rv = __shfl(row, 4 * q + v, 64);
+            const float *cr = a.Cst[n] + (int64_t)rv * R16 + c;
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) in.C[n][rb][v] = cr[16 * rb];
+        }
+    }
+    const int64_t s0 = base + 4 * q;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) in.x[v] = s0 + v <= last ? a.val[s0 + v] : 0.f;
+}
+
+template <int N, int KQ, int RB>
+__global__ __launch_bounds__(256) void core_grad_stored_kernel(
+    CoreArgs a, int64_t ntiles) {
+    constexpr int J4 = 4 * KQ;
+    constexpr int R16 = 16 * RB;
+    constexpr int JB = (KQ + 3) / 4;
+    constexpr int TP = J4 + 1;
+    extern __shared__ float lds[];
+    const int lane = threadIdx.x & 63, q = lane >> 4, c = lane & 15;
+    const int wave = threadIdx.x >> 6;
+    constexpr int WAVE_LDS = (N * J4 * R16 > N * 16 * TP) ? N * J4 * R16
+                                                          : N * 16 * TP;
+    float *tr = lds + wave * WAVE_LDS;
+    floatx4 grad[N][JB][RB];
+#pragma unroll
+    for (int n = 0; n < N; ++n)
+#pragma unroll
+        for (int jb = 0; jb < JB; ++jb)
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb)
+                grad[n][jb][rb] = floatx4{0.f, 0.f, 0.f, 0.f};
+    double loss = 0.0;
+    const int64_t nwaves = (int64_t)gridDim.x * 4;
+    const int64_t last = a.count - 1;
+    int64_t tile = (int64_t)blockIdx.x * 4 + wave;
+    StoredTileIn<N, KQ, RB> nxt;
+    if (tile < ntiles) load_stored_tile<N, KQ, RB>(a, tile, q, c, nxt);
+    for (; tile < ntiles; tile += nwaves) {
+        const StoredTileIn<N, KQ, RB> cur = nxt;
+        if (tile + nwaves < ntiles)
+            load_stored_tile<N, KQ, RB>(a, tile + nwaves, q, c, nxt);
+        const int64_t base = tile * 16;
+        floatx4 D[N][RB];
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+            floatx4 pre = {1.f, 1.f, 1.f, 1.f};
+#pragma unroll
+            for (int n = 0; n < N; ++n) {
+                D[n][rb] = pre;
+                pre *= cur.C[n][rb];
+            }
+            floatx4 suf = {1.f, 1.f, 1.f, 1.f};
+#pragma unroll
+            for (int n = N - 1; n >= 0; --n) {
+                D[n][rb] *= suf;
+                suf *= cur.C[n][rb];
+            }
+        }
+        float r[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            float xh = 0.f;
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb)
+                xh += cur.C[0][rb][v] * D[0][rb][v];
+            xh = sum_row16(xh);
+            const bool ok = base + 4 * q + v <= last;
+            r[v] = ok ? xh - cur.x[v] : 0.f;
+            if (c == 0 && ok) loss += 0.5 * (double)r[v] * (double)r[v];
+        }
+        wave_lds_sync();
+#pragma unroll
+        for (int n = 0; n < N; ++n)
+#pragma unroll
+            for (int t = 0; t < KQ; ++t)
+                tr[(n * 16 + c) * TP + KQ * q + t] = cur.arow[n].value(t);
+        wave_lds_sync();
+#pragma unroll
+        for (int n = 0; n < N; ++n) {
+#pragma unroll
+            for (int jb = 0; jb < JB; ++jb) {
+                const int j = 16 * jb + c;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const float av =
+                        j < J4 ? tr[(n * 16 + 4 * q + v) * TP + j] : 0.f;
+                    const float e = r[v] * av;
+#pragma unroll
+                    for (int rb = 0; rb < RB; ++rb)
+                        grad[n][jb][rb] =
+                            mfma_16x16x4(e, D[n][rb][v], grad[n][jb][rb]);
+                }
+            }
+        }
+    }
+    wave_lds_sync();
+    __syncthreads();
+    float *mine = lds + wave * (N * J4 * R16);
+#pragma unroll
+    for (int n = 0; n < N; ++n)
+#pragma unroll
+        for (int jb = 0; jb < JB; ++jb)
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int j = 16 * jb + 4 * q + v;
+                    if (j < J4)
+                        mine[(n * J4 + j) * R16 + 16 * rb + c] =
+                            grad[n][jb][rb][v];
+                }
+    __syncthreads();
+    constexpr int E = N * J4 * R16;
+    float *out = a.part + (int64_t)blockIdx.x * E;
+    for (int e = threadIdx.x; e < E; e += 256)
+        out[e] = ((lds[e] + lds[E + e]) + lds[2 * E + e]) + lds[3 * E + e];
+    const double tot = block_sum_256(loss);
+    if (threadIdx.x == 0) a.loss_part[blockIdx.x] = tot;
+}
+
+template <int J4, int R16>
+static hipError_t launch_pc(const float *A, const float *B, int64_t rows,
+                            float *Cst, hipStream_t s) {
+    const int64_t threads = rows * (R16 / 4);
+    const int64_t blocks = (threads + 255) / 256;
+    FT_LAUNCH((precompute_c_kernel<J4, R16>), dim3((unsigned)blocks),
+              dim3(256), 0, s, A, B, rows, Cst);
+    return hipGetLastError();
+}
+
+template <int J4>
+static hipError_t launch_pc_r(int R16, const float *A, const float *B,
+                              int64_t rows, float *Cst, hipStream_t s) {
+    return R16 == 16 ? launch_pc<J4, 16>(A, B, rows, Cst, s)
+                     : launch_pc<J4, 32>(A, B, rows, Cst, s);
+}
+
+hipError_t launch_precompute_c(const Shape &sh, const float *A, const float *B,
+                               int64_t rows, float *Cst, hipStream_t s) {
+    if (rows < 1) return hipSuccess;
+    switch (sh.J4) {
+    case 4: return launch_pc_r<4>(sh.R16, A, B, rows, Cst, s);
+    case 8: return launch_pc_r<8>(sh.R16, A, B, rows, Cst, s);
+    case 12: return launch_pc_r<12>(sh.R16, A, B, rows, Cst, s);
+    case 16: return launch_pc_r<16>(sh.R16, A, B, rows, Cst, s);
+    case 20: return launch_pc_r<20>(sh.R16, A, B, rows, Cst, s);
+    case 24: return launch_pc_r<24>(sh.R16, A, B, rows, Cst, s);
+    case 28: return launch_pc_r<28>(sh.R16, A, B, rows, Cst, s);
+    case 32: return launch_pc_r<32>(sh.R16, A, B, rows, Cst, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <int N, int KQ, int RB>
+static hipError_t launch_cgs(const CoreArgs &a, int blocks, hipStream_t s) {
+    const int64_t ntiles = (a.count + 15) / 16;
+    const int part = N * (4 * KQ) * (16 * RB);
+    const int trans = N * 16 * (4 * KQ + 1);
+    const size_t lds = sizeof(float) * 4 * (part > trans ? part : trans);
+    const int fit = resident_blocks(
+        reinterpret_cast<const void *>(&core_grad_stored_kernel<N, KQ, RB>),
+        lds);
+    if (blocks > fit) blocks = fit;
+    *a.blocks_used = blocks;
+    FT_LAUNCH((core_grad_stored_kernel<N, KQ, RB>), dim3(blocks), dim3(256),
+              lds, s, a, ntiles);
+    return hipGetLastError();
+}
+
+template <int N, int KQ>
+static hipError_t launch_cgs_r(const Shape &sh, const CoreArgs &a, int blocks,
+                               hipStream_t s) {
+    return sh.R16 == 16 ? launch_cgs<N, KQ, 1>(a, blocks, s)
+                        : launch_cgs<N, KQ, 2>(a, blocks, s);
+}
+
+template <int N>
+static hipError_t launch_cgs_j(const Shape &sh, const CoreArgs &a, int blocks,
+                               hipStream_t s) {
+    switch (sh.J4) {
+    case 4: return launch_cgs_r<N, 1>(sh, a, blocks, s);
+    case 8: return launch_cgs_r<N, 2>(sh, a, blocks, s);
+    case 12: return launch_cgs_r<N, 3>(sh, a, blocks, s);
+    case 16: return launch_cgs_r<N, 4>(sh, a, blocks, s);
+    case 20: return launch_cgs_r<N, 5>(sh, a, blocks, s);
+    case 24: return launch_cgs_r<N, 6>(sh, a, blocks, s);
+    case 28: return launch_cgs_r<N, 7>(sh, a, blocks, s);
+    case 32: return launch_cgs_r<N, 8>(sh, a, blocks, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_core_grad_stored(const Shape &sh, const CoreArgs &a,
+                                   int nblocks, hipStream_t s) {
+    if (sh.prec != kF32) return hipErrorInvalidValue;
+    if (nblocks > kCoreMaxBlocks) nblocks = kCoreMaxBlocks;
+    switch (sh.N) {
+    case 2: return launch_cgs_j<2>(sh, a, nblocks, s);
+    case 3: return launch_cgs_j<3>(sh, a, nblocks, s);
+    case 4: return launch_cgs_j<4>(sh, a, nblocks, s);
+    case 5: return launch_cgs_j<5>(sh, a, nblocks, s);
     }
     return hipErrorInvalidValue;
 }

@@ -88,28 +88,42 @@ static hipError_t launch_ev_p(const Shape &sh, const EvalArgs &a, int blocks,
 template <int N, int KQ>
 static hipError_t launch_ev_r(const Shape &sh, const EvalArgs &a, int blocks,
                               hipStream_t s) {
-    switch (sh.prec) {
-    case kF32: return launch_ev_p<N, KQ, kF32>(sh, a, blocks, s);
-    case kBF16: return launch_ev_p<N, KQ, kBF16>(sh, a, blocks, s);
-    case kFP8: return launch_ev_p<N, KQ, kFP8>(sh, a, blocks, s);
+    if constexpr (N > kFullOrder) {  // FP32 only above the full orders
+        return sh.prec == kF32 ? launch_ev_p<N, KQ, kF32>(sh, a, blocks, s)
+                               : hipErrorInvalidValue;
+    } else {
+        switch (sh.prec) {
+        case kF32: return launch_ev_p<N, KQ, kF32>(sh, a, blocks, s);
+        case kBF16: return launch_ev_p<N, KQ, kBF16>(sh, a, blocks, s);
+        case kFP8: return launch_ev_p<N, KQ, kFP8>(sh, a, blocks, s);
+        }
+        return hipErrorInvalidValue;
     }
-    return hipErrorInvalidValue;
 }
 
 template <int N>
 static hipError_t launch_ev_j(const Shape &sh, const EvalArgs &a, int blocks,
                               hipStream_t s) {
-    switch (sh.J4) {
-    case 4: return launch_ev_r<N, 1>(sh, a, blocks, s);
-    case 8: return launch_ev_r<N, 2>(sh, a, blocks, s);
-    case 12: return launch_ev_r<N, 3>(sh, a, blocks, s);
-    case 16: return launch_ev_r<N, 4>(sh, a, blocks, s);
-    case 20: return launch_ev_r<N, 5>(sh, a, blocks, s);
-    case 24: return launch_ev_r<N, 6>(sh, a, blocks, s);
-    case 28: return launch_ev_r<N, 7>(sh, a, blocks, s);
-    case 32: return launch_ev_r<N, 8>(sh, a, blocks, s);
+    if constexpr (N > kFullOrder) {   // J4 padded to 8, 16 or 32
+        switch (sh.J4) {
+        case 8: return launch_ev_r<N, 2>(sh, a, blocks, s);
+        case 16: return launch_ev_r<N, 4>(sh, a, blocks, s);
+        case 32: return launch_ev_r<N, 8>(sh, a, blocks, s);
+        }
+        return hipErrorInvalidValue;
+    } else {
+        switch (sh.J4) {
+        case 4: return launch_ev_r<N, 1>(sh, a, blocks, s);
+        case 8: return launch_ev_r<N, 2>(sh, a, blocks, s);
+        case 12: return launch_ev_r<N, 3>(sh, a, blocks, s);
+        case 16: return launch_ev_r<N, 4>(sh, a, blocks, s);
+        case 20: return launch_ev_r<N, 5>(sh, a, blocks, s);
+        case 24: return launch_ev_r<N, 6>(sh, a, blocks, s);
+        case 28: return launch_ev_r<N, 7>(sh, a, blocks, s);
+        case 32: return launch_ev_r<N, 8>(sh, a, blocks, s);
+        }
+        return hipErrorInvalidValue;
     }
-    return hipErrorInvalidValue;
 }
 
 hipError_t launch_eval(const Shape &sh, const EvalArgs &a, int nblocks,
@@ -119,6 +133,11 @@ hipError_t launch_eval(const Shape &sh, const EvalArgs &a, int nblocks,
     case 3: return launch_ev_j<3>(sh, a, nblocks, s);
     case 4: return launch_ev_j<4>(sh, a, nblocks, s);
     case 5: return launch_ev_j<5>(sh, a, nblocks, s);
+    case 6: return launch_ev_j<6>(sh, a, nblocks, s);
+    case 7: return launch_ev_j<7>(sh, a, nblocks, s);
+    case 8: return launch_ev_j<8>(sh, a, nblocks, s);
+    case 9: return launch_ev_j<9>(sh, a, nblocks, s);
+    case 10: return launch_ev_j<10>(sh, a, nblocks, s);
     }
     return hipErrorInvalidValue;
 }

@@ -239,8 +239,11 @@ __device__ __forceinline__ void stage_B(const float *const *B, float *sB,
 // shapes; two is reached by every shape without spilling or scratch
 // (checked per instantiation at build time). Asking for three where it
 // fits (order 4, J = R = 32) made the kernel faster but slowed the builder
-// running beside it, and the epoch with it.
-constexpr int factor_waves(int, int, int, int) { return 2; }
+// running beside it, and the epoch with it. Order 10 at J = 16, R = 32 needs
+// one wave per SIMD to stay in registers.
+constexpr int factor_waves(int N, int KQ, int RB, int) {
+    return N > kFullOrder && N * KQ * RB >= 80 ? 1 : 2;   // (order 10)
+}
 
 template <int N, int KQ, int RB, int P>
 __global__ __launch_bounds__(kFactorThreads)
@@ -499,28 +502,42 @@ static hipError_t launch_fg_p(const Shape &sh, const FactorArgs &a, int blocks,
 template <int N, int KQ>
 static hipError_t launch_fg_r(const Shape &sh, const FactorArgs &a, int blocks,
                               hipStream_t s) {
-    switch (sh.prec) {
-    case kF32: return launch_fg_p<N, KQ, kF32>(sh, a, blocks, s);
-    case kBF16: return launch_fg_p<N, KQ, kBF16>(sh, a, blocks, s);
-    case kFP8: return launch_fg_p<N, KQ, kFP8>(sh, a, blocks, s);
+    if constexpr (N > kFullOrder) {  // FP32 only above the full orders
+        return sh.prec == kF32 ? launch_fg_p<N, KQ, kF32>(sh, a, blocks, s)
+                               : hipErrorInvalidValue;
+    } else {
+        switch (sh.prec) {
+        case kF32: return launch_fg_p<N, KQ, kF32>(sh, a, blocks, s);
+        case kBF16: return launch_fg_p<N, KQ, kBF16>(sh, a, blocks, s);
+        case kFP8: return launch_fg_p<N, KQ, kFP8>(sh, a, blocks, s);
+        }
+        return hipErrorInvalidValue;
     }
-    return hipErrorInvalidValue;
 }
 
 template <int N>
 static hipError_t launch_fg_j(const Shape &sh, const FactorArgs &a, int blocks,
                               hipStream_t s) {
-    switch (sh.J4) {
-    case 4: return launch_fg_r<N, 1>(sh, a, blocks, s);
-    case 8: return launch_fg_r<N, 2>(sh, a, blocks, s);
-    case 12: return launch_fg_r<N, 3>(sh, a, blocks, s);
-    case 16: return launch_fg_r<N, 4>(sh, a, blocks, s);
-    case 20: return launch_fg_r<N, 5>(sh, a, blocks, s);
-    case 24: return launch_fg_r<N, 6>(sh, a, blocks, s);
-    case 28: return launch_fg_r<N, 7>(sh, a, blocks, s);
-    case 32: return launch_fg_r<N, 8>(sh, a, blocks, s);
+    if constexpr (N > kFullOrder) {   // J4 padded to 8, 16 or 32
+        switch (sh.J4) {
+        case 8: return launch_fg_r<N, 2>(sh, a, blocks, s);
+        case 16: return launch_fg_r<N, 4>(sh, a, blocks, s);
+        case 32: return launch_fg_r<N, 8>(sh, a, blocks, s);
+        }
+        return hipErrorInvalidValue;
+    } else {
+        switch (sh.J4) {
+        case 4: return launch_fg_r<N, 1>(sh, a, blocks, s);
+        case 8: return launch_fg_r<N, 2>(sh, a, blocks, s);
+        case 12: return launch_fg_r<N, 3>(sh, a, blocks, s);
+        case 16: return launch_fg_r<N, 4>(sh, a, blocks, s);
+        case 20: return launch_fg_r<N, 5>(sh, a, blocks, s);
+        case 24: return launch_fg_r<N, 6>(sh, a, blocks, s);
+        case 28: return launch_fg_r<N, 7>(sh, a, blocks, s);
+        case 32: return launch_fg_r<N, 8>(sh, a, blocks, s);
+        }
+        return hipErrorInvalidValue;
     }
-    return hipErrorInvalidValue;
 }
 
 hipError_t launch_factor_grad(const Shape &sh, const FactorArgs &a, int *nblocks,
@@ -532,6 +549,11 @@ hipError_t launch_factor_grad(const Shape &sh, const FactorArgs &a, int *nblocks
     case 3: return launch_fg_j<3>(sh, a, blocks, s);
     case 4: return launch_fg_j<4>(sh, a, blocks, s);
     case 5: return launch_fg_j<5>(sh, a, blocks, s);
+    case 6: return launch_fg_j<6>(sh, a, blocks, s);
+    case 7: return launch_fg_j<7>(sh, a, blocks, s);
+    case 8: return launch_fg_j<8>(sh, a, blocks, s);
+    case 9: return launch_fg_j<9>(sh, a, blocks, s);
+    case 10: return launch_fg_j<10>(sh, a, blocks, s);
     }
     return hipErrorInvalidValue;
 }

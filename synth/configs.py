@@ -105,15 +105,17 @@ CONFIGS = {
 }
 
 
-# Order and rank sweep in the manner of the paper's scaling study (Fig. 2,
-# Table 10): I_n = 10,000 in every mode, J = R in {16, 32}, orders 3..5
-# (the device path covers N <= 5), ratings 1..5 from a planted model, uniform
-# indices; 10M nonzeros (the paper's 1e8 scaled down tenfold), M = 65,536.
-for _n in (3, 4, 5):
-    for _r in (16, 32):
+# Order and rank sweep of the paper's synthetic study (Table 5, Fig. 2):
+# I_n = 10,000 in every mode, |Omega| = 1e8, ratings 1..5 (from a planted
+# model, uniform indices; the paper gives no value distribution), orders
+# 3..10 at J = R = 16 (the paper's setting), and J = R = 32 at orders 3..5
+# for the rank comparison. M = 65,536. Throughput workloads: the step sizes
+# are not tuned for them.
+for _n in range(3, 11):
+    for _r in ((16, 32) if _n <= 5 else (16,)):
         CONFIGS[f"sweep-N{_n}-R{_r}"] = Workload(
-            name=f"sweep-order{_n}-1e4^{_n}-10M-uniform-rating-J{_r}R{_r}",
-            dims=(10_000,) * _n, nnz=10_000_000, J=_r, R=_r, M=65_536,
+            name=f"sweep-order{_n}-1e4^{_n}-100M-uniform-rating-J{_r}R{_r}",
+            dims=(10_000,) * _n, nnz=100_000_000, J=_r, R=_r, M=65_536,
             epochs=5, lr_A=0.01, lr_B=0.1, lam_A=1e-3, lam_B=1e-3,
             row_mean=True, index_dist="uniform", values="rating",
             rating_offset=3.0, noise_std=0.3, planted_rank=_r,

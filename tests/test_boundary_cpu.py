@@ -31,7 +31,7 @@ def test_header_declarations_are_exported():
 
 
 def test_options_struct_layout():
-    assert C.sizeof(_lib.Options) == 72
+    assert C.sizeof(_lib.Options) == 80
     lib = _lib.load()
     o = _lib.Options()
     assert lib.ft_default_options(C.byref(o)) == 0
@@ -53,7 +53,9 @@ def _create(order, dims, J, R):
 
 @pytest.mark.parametrize("order,dims,J,R,needle", [
     (1, [10], [4], 4, "order"),
-    (6, [3] * 6, [2] * 6, 2, "order"),
+    (11, [3] * 11, [2] * 11, 2, "order"),
+    (7, [3] * 7, [32] * 7, 32, "LDS"),
+    (10, [3] * 10, [17] * 10, 20, "LDS"),
     (3, [10, 0, 10], [4, 4, 4], 4, "dims[1]"),
     (3, [10, 10, 10], [4, 0, 4], 4, "J[1]"),
     (3, [10, 10, 10], [4, 33, 4], 4, "J[1]"),

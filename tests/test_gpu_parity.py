@@ -45,6 +45,18 @@ W = {
     "M1": synth.get("c0", name="m1", dims=(5, 6, 7), nnz=60, J=4, R=4, M=1),
     "nnz_lt_M": synth.get("c0", name="small", dims=(20, 20, 20), nnz=120,
                           J=4, R=4, M=512),
+    # orders above 5 (FP32 verify path, J4 padded to 8 / 16 / 32)
+    "order6": synth.get("c0", name="o6", dims=(12, 10, 9, 8, 7, 6),
+                        nnz=3000, J=8, R=16, M=400, init_a_std=0.6,
+                        init_b_std=0.6),
+    "order8_J12_R20": synth.get("c0", name="o8", dims=(9, 8, 7, 6, 5, 6, 7,
+                                                       8),
+                                nnz=3000, J=12, R=20, M=512, init_a_std=0.6,
+                                init_b_std=0.6),
+    "order10_J16": synth.get("c0", name="o10", dims=(6, 5, 7, 4, 6, 5, 4, 6,
+                                                     5, 7),
+                             nnz=4000, J=16, R=16, M=700, init_a_std=0.6,
+                             init_b_std=0.6),
     # rows of ~20,000-30,000 samples per minibatch: long crossing rows
     # summed in several parts and combined
     "hot": synth.get("c0", name="hot", dims=(2000, 1500, 4), nnz=250_000,
@@ -59,7 +71,8 @@ def perm_for(w, T, epoch=0):
 
 # ----------------------------------------------------------------- eval
 @pytest.mark.parametrize("name", ["c0", "pad_J3_R5", "order5_J32_R32",
-                                  "J12_R20"])
+                                  "J12_R20", "order6", "order8_J12_R20",
+                                  "order10_J16"])
 def test_eval_and_loss(name):
     w = W[name]
     ft, T, A0, B0 = setup(w)
@@ -138,7 +151,8 @@ def test_factor_minibatch_gradients(name):
 @pytest.mark.parametrize("name,row_mean", [("c0", False), ("c0", True),
                                            ("zipf", True), ("order4", False),
                                            ("pad_J3_R5", True), ("hot", True),
-                                           ("hot", False)])
+                                           ("hot", False), ("order6", True),
+                                           ("order10_J16", False)])
 def test_factor_minibatch_update(name, row_mean):
     w = W[name]
     ft, T, A0, B0 = setup(w, with_test=False)
@@ -163,7 +177,8 @@ def test_factor_minibatch_update(name, row_mean):
         assert np.linalg.norm(d_gpu - d_orc) <= tol, n
 
 
-@pytest.mark.parametrize("name", ["c0", "order4", "zipf"])
+@pytest.mark.parametrize("name", ["c0", "order4", "zipf", "order6",
+                                  "order10_J16"])
 def test_free_running_epochs(name):
     """Alternating factor and core epochs on both sides from the same start
     and orders: per-epoch train/test RMSE to 1e-4, first-epoch minibatch
@@ -193,7 +208,8 @@ def test_free_running_epochs(name):
 
 # ----------------------------------------------------------------- core
 @pytest.mark.parametrize("name", ["c0", "pad_J3_R5", "order2", "order4",
-                                  "order5_J32_R32", "J12_R20", "zipf"])
+                                  "order5_J32_R32", "J12_R20", "zipf",
+                                  "order6", "order8_J12_R20", "order10_J16"])
 def test_core_gradient_and_update(name):
     w = W[name]
     ft, T, A0, B0 = setup(w, with_test=False)
@@ -609,3 +625,126 @@ def test_vector_alu_rejects_unsupported_settings():
     ft.set_options(precision=0, deterministic=0)
     with pytest.raises(FtError):
         ft.set_options(vector_alu=1)          # Hogwild fast mode
+
+
+# ----------------------------------------------------------------- storage
+@pytest.mark.parametrize("name", ["c0", "pad_J3_R5", "order2", "order4",
+                                  "order5_J32_R32", "J12_R20", "zipf", "M1",
+                                  "nnz_lt_M"])
+def test_core_storage_variant_matches_oracle(name):
+    """The storage form of the core phase (C = A B stored once per pass, rows
+    of C gathered per sample) gives the oracle's core loss, gradient and
+    update to the calculation form's tolerances."""
+    w = W[name]
+    ft, T, A0, B0 = setup(w, with_test=False)
+    ft.set_options(core_storage=1)
+    A, B = f64(A0), f64(B0)
+    tv = T.train_val.astype(np.float64)
+    loss, G = ft.core_grad()
+    oloss, OG = oracle.core_grad(A, B, T.train_idx, tv)
+    assert loss == pytest.approx(oloss, rel=LOSS_RTOL)
+    for n in range(w.order):
+        assert rel_norm([G[n]], [OG[n]]) < GRAD_RTOL, n
+    cl = ft.epoch_core()
+    assert cl == pytest.approx(oloss, rel=LOSS_RTOL)
+    oracle.core_epoch(A, B, T.train_idx, tv, w.lr_B, w.lam_B)
+    A1, B1 = ft.get_params()
+    for n in range(w.order):
+        np.testing.assert_array_equal(A1[n], A0[n])
+        d_gpu = B1[n].astype(np.float64) - B0[n]
+        d_orc = B[n] - B0[n]
+        tol = GRAD_RTOL * np.linalg.norm(d_orc) + \
+            2 * EPS32 * np.linalg.norm(B[n])
+        assert np.linalg.norm(d_gpu - d_orc) <= tol, n
+
+
+def test_core_storage_per_minibatch_steps_and_free_running():
+    """Per-minibatch core steps re-store C after every step of B; free-
+    running alternating epochs with the storage form track the oracle's
+    per-epoch RMSE to 1e-4."""
+    w = W["zipf"]
+    ft, T, A0, B0 = setup(w)
+    ft.set_options(core_storage=1, core_step=FT_CORE_PER_MINIBATCH)
+    p = perm_for(w, T, 2)
+    ft.set_epoch_order(p)
+    A, B = f64(A0), f64(B0)
+    tv = T.train_val.astype(np.float64)
+    cl = ft.epoch_core()
+    ocl = oracle.core_epoch(A, B, T.train_idx, tv, w.lr_B, w.lam_B, perm=p,
+                            M=w.M, per_minibatch=True)
+    assert cl == pytest.approx(ocl, rel=RMSE_RTOL)
+    _, B1 = ft.get_params()
+    assert rel_norm(B1, B) < RMSE_RTOL
+    ft.set_options(core_step=0)
+    sv = T.test_val.astype(np.float64)
+    for ep in range(3):
+        p = perm_for(w, T, ep)
+        ft.set_epoch_order(p)
+        ft.epoch_factors()
+        ft.epoch_core()
+        oracle.factor_epoch(A, B, T.train_idx, tv, p, w.M, w.lr_A, w.lam_A,
+                            w.row_mean)
+        oracle.core_epoch(A, B, T.train_idx, tv, w.lr_B, w.lam_B)
+        osse, _ = oracle.residual_stats(A, B, T.test_idx, sv)
+        assert ft.rmse(FT_TEST) == pytest.approx(np.sqrt(osse / len(sv)),
+                                                 rel=RMSE_RTOL), ep
+
+
+def test_core_storage_rejects_unsupported_settings():
+    ft, _, _, _ = setup(W["c0"], with_test=False)
+    for bad in ({"precision": 1}, {"deterministic": 0}, {"vector_alu": 1}):
+        ft.set_options(precision=0, deterministic=1, vector_alu=0,
+                       core_storage=0)
+        ft.set_options(**bad)
+        with pytest.raises(FtError):
+            ft.set_options(core_storage=1)
+
+
+# ----------------------------------------------------------------- high orders
+def test_high_order_unequal_ranks_and_builder():
+    """Order 7 with unequal J_n (A rows padded to 16) and R = 24: minibatch
+    gradients and counts, the core gradient, and the bit-exact builder
+    (records of 16 words above order 7 are exercised by order 8 and 10)."""
+    dims, J, R = (9, 11, 8, 7, 10, 6, 5), (3, 12, 5, 7, 2, 9, 4), 24
+    T = synth.make_tensor(synth.get("c0", dims=dims, nnz=3000, J=4, R=4))
+    A0, B0 = synth.init_params(19, dims, list(J), R, 0.7)
+    ft = FastTucker(dims, list(J), R)
+    ft.set_options(minibatch=256, lr_A=0.02, lambda_A=0.01, shuffle_seed=8)
+    ft.set_nonzeros(FT_TRAIN, T.train_idx, T.train_val)
+    ft.set_params(A0, B0)
+    ft.prepare_epoch()
+    perm = ft.epoch_order()
+    nnz = T.train_idx.shape[1]
+    np.testing.assert_array_equal(perm,
+                                  _ref.feistel_order(nnz, _ref.epoch_key(8, 0)))
+    for b in (0, ft.num_minibatches() - 1):
+        loss, G, K = ft.factor_minibatch(b, apply=False)
+        s = perm[b * 256:(b + 1) * 256]
+        idx = np.ascontiguousarray(T.train_idx[:, s])
+        val = T.train_val[s].astype(np.float64)
+        ol, OG, OK = oracle.factor_minibatch(f64(A0), f64(B0), idx, val, 0.02,
+                                             0.01, False, apply=False,
+                                             want_grad=True)
+        assert loss == pytest.approx(ol, rel=LOSS_RTOL)
+        for n in range(7):
+            np.testing.assert_array_equal(K[n], OK[n])
+            assert rel_norm([G[n]], [OG[n]]) < GRAD_RTOL, (b, n)
+            pos, rows = ft.minibatch_sort(b, n)
+            rpos, rrows = _ref.minibatch_sort(T.train_idx[n, s])
+            np.testing.assert_array_equal(pos, rpos)
+            np.testing.assert_array_equal(rows, rrows)
+    l2, CG = ft.core_grad()
+    _, OCG = oracle.core_grad(f64(A0), f64(B0), T.train_idx,
+                              T.train_val.astype(np.float64))
+    for n in range(7):
+        assert rel_norm([CG[n]], [OCG[n]]) < GRAD_RTOL, n
+
+
+@pytest.mark.parametrize("opts", [{"precision": 1}, {"precision": 2},
+                                  {"deterministic": 0}, {"vector_alu": 1},
+                                  {"core_storage": 1}])
+def test_high_orders_reject_the_variants(opts):
+    ft, _, _, _ = setup(W["order6"], with_test=False)
+    with pytest.raises(FtError) as e:
+        ft.set_options(**opts)
+    assert e.value.status == 1

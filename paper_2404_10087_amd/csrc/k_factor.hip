@@ -313,7 +313,11 @@ factor_grad_kernel(
 // waves sweep all 16-sample tiles of the epoch order with no minibatch
 // barrier; each tile reads its rows, forms g, and applies
 // a <- a - lr_A (g + lambda_A a) at once with hardware float atomics, so
-// concurrent tiles race on shared rows by design. One FP64 loss per tile.
+// concurrent tiles race on shared rows by design. Samples of one tile that
+// share a row are summed first (lane shuffles) and the row takes one step
+// a <- a - lr_A (sum g + k lambda_A a): the tile is a Jacobi step of 16
+// samples, and a hot row takes one atomic per tile instead of one per
+// sample. One FP64 loss per tile.
 template <int N, int KQ, int RB>
 __global__ __launch_bounds__(kFactorThreads) void hogwild_kernel(HogArgs a) {
     using T = FactorTile<N, KQ, RB, kF32>;
@@ -340,15 +344,40 @@ __global__ __launch_bounds__(kFactorThreads) void hogwild_kernel(HogArgs a) {
         if ((threadIdx.x & 63) == 0) a.tile_loss[tile] = tl_loss;
 #pragma unroll
         for (int n = 0; n < N; ++n) {
+            // the tile's samples on this lane's row (bit k: sample k; lane k
+            // holds sample k); padding lanes match nothing
+            const int myrow = valid ? rows[n] : -1 - tl.c;
+            uint32_t peers = 0;
+#pragma unroll
+            for (int k = 0; k < 16; ++k)
+                peers |= (__shfl(myrow, k) == myrow ? 1u : 0u) << k;
+            const bool leader = (peers & ((1u << tl.c) - 1u)) == 0u;
+            const int cnt = __popc(peers);
+            const bool dup = __ballot(cnt > 1) != 0ull;   // wave-uniform
 #pragma unroll
             for (int jb = 0; jb < T::JB; ++jb) {
-                const floatx4 g = tl.grad(n, jb, r);
+                floatx4 g = tl.grad(n, jb, r);
+                if (dup) {
+                    // one step per row and tile: the sum of its samples'
+                    // gradients, applied by the first of them
+                    floatx4 sum = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                    for (int k = 0; k < 16; ++k) {
+                        floatx4 gk;
+#pragma unroll
+                        for (int v = 0; v < 4; ++v)
+                            gk[v] = __shfl(g[v], 16 * tl.q + k);
+                        if ((peers >> k) & 1u) sum += gk;
+                    }
+                    g = sum;
+                }
                 const int j0 = 16 * jb + 4 * tl.q;
-                if (valid && j0 < T::J4) {
+                if (valid && leader && j0 < T::J4) {
                     float *ap = a.A[n] + (int64_t)rows[n] * T::J4 + j0;
 #pragma unroll
                     for (int v = 0; v < 4; ++v)
-                        unsafeAtomicAdd(ap + v, -a.lr * (g[v] + a.lam * ap[v]));
+                        unsafeAtomicAdd(ap + v, -a.lr * (g[v] + (float)cnt *
+                                                         a.lam * ap[v]));
                 }
             }
         }

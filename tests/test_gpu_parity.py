@@ -45,18 +45,19 @@ W = {
     "M1": synth.get("c0", name="m1", dims=(5, 6, 7), nnz=60, J=4, R=4, M=1),
     "nnz_lt_M": synth.get("c0", name="small", dims=(20, 20, 20), nnz=120,
                           J=4, R=4, M=512),
-    # orders above 5 (FP32 verify path, J4 padded to 8 / 16 / 32)
+    # orders above 5 (FP32 verify path, J4 padded to 8 / 16 / 32); an
+    # initial spread of 0.6 makes these products diverge on both sides
     "order6": synth.get("c0", name="o6", dims=(12, 10, 9, 8, 7, 6),
-                        nnz=3000, J=8, R=16, M=400, init_a_std=0.6,
-                        init_b_std=0.6),
+                        nnz=3000, J=8, R=16, M=400, init_a_std=0.45,
+                        init_b_std=0.45),
     "order8_J12_R20": synth.get("c0", name="o8", dims=(9, 8, 7, 6, 5, 6, 7,
                                                        8),
-                                nnz=3000, J=12, R=20, M=512, init_a_std=0.6,
-                                init_b_std=0.6),
+                                nnz=3000, J=12, R=20, M=512, init_a_std=0.45,
+                                init_b_std=0.45),
     "order10_J16": synth.get("c0", name="o10", dims=(6, 5, 7, 4, 6, 5, 4, 6,
                                                      5, 7),
-                             nnz=4000, J=16, R=16, M=700, init_a_std=0.6,
-                             init_b_std=0.6),
+                             nnz=4000, J=16, R=16, M=700, init_a_std=0.45,
+                             init_b_std=0.45),
     # rows of ~20,000-30,000 samples per minibatch: long crossing rows
     # summed in several parts and combined
     "hot": synth.get("c0", name="hot", dims=(2000, 1500, 4), nnz=250_000,

@@ -735,7 +735,7 @@ static ft_status build_minibatches(ft_handle *h, EpochBufs &E, hipStream_t s,
     HIPCHK(h, ensure(&E.counts, &E.counts_cap,
                      (size_t)h->N * nseg * kRadix * tps));
     const int xcap = cross_capacity(std::min<int64_t>(M, nnz));
-    const int pcap = part_capacity(std::min<int64_t>(M, nnz));
+    const int pcap = part_capacity(std::min<int64_t>(M, nnz), h->sh.J4);
     HIPCHK(h, ensure(&E.xlist, &E.xlist_cap, (size_t)nseg * h->N * xcap));
     HIPCHK(h, ensure(&E.plist, &E.plist_cap, (size_t)nseg * h->N * pcap));
     HIPCHK(h, ensure(&E.xcount, &E.xcount_cap, nx));
@@ -796,6 +796,7 @@ static ft_status build_minibatches(ft_handle *h, EpochBufs &E, hipStream_t s,
     cx.pcap = pcap;
     cx.xcount = E.xcount;
     cx.grid_cap = cap;
+    cx.J4 = h->sh.J4;
     E.xcap = xcap;
     E.pcap = pcap;
     HIPCHK(h, launch_crossing_segments(cx, s));
@@ -974,7 +975,7 @@ static ft_status alloc_factor(ft_handle *h, int64_t nmb, int nper) {
     (void)nch;
     HIPCHK(h, ensure(&h->G, &h->G_cap, (size_t)h->N * M * h->sh.J4));
     HIPCHK(h, ensure(&h->P, &h->P_cap,
-                     (size_t)h->N * part_capacity(M) * h->sh.J4));
+                     (size_t)h->N * part_capacity(M, h->sh.J4) * h->sh.J4));
     HIPCHK(h, ensure(&h->mb_part, &h->mb_part_cap, (size_t)nmb * nper));
     HIPCHK(h, ensure(&h->mb_loss, &h->mb_loss_cap, (size_t)nmb));
     return FT_OK;
@@ -1043,7 +1044,7 @@ extern "C" ft_status ft_epoch_factors(ft_handle *h, double *mb_loss) {
     }
     const int64_t nmb = nminibatches(h);
     const int nper = factor_grad_blocks(
-        (int32_t)std::min<int64_t>(h->opt.minibatch, h->nnz[FT_TRAIN]));
+        h->sh, (int32_t)std::min<int64_t>(h->opt.minibatch, h->nnz[FT_TRAIN]));
     ft_status st = alloc_factor(h, nmb, nper);
     if (st != FT_OK) return st;
     HIPCHK(h, hipMemsetAsync(h->mb_part, 0, sizeof(double) * nmb * nper,
@@ -1090,7 +1091,7 @@ extern "C" ft_status ft_factor_minibatch(ft_handle *h, int64_t b,
             if (!grad[n] || !count[n])
                 return fail(h, FT_EINVAL, "grad[%d] or count[%d] is NULL", n, n);
     const int nper = factor_grad_blocks(
-        (int32_t)std::min<int64_t>(h->opt.minibatch, h->nnz[FT_TRAIN]));
+        h->sh, (int32_t)std::min<int64_t>(h->opt.minibatch, h->nnz[FT_TRAIN]));
     ft_status st = alloc_factor(h, nmb, nper);
     if (st != FT_OK) return st;
     float *dgrad[kMaxOrder] = {};
@@ -1494,7 +1495,7 @@ MbLayout mb_layout(const ft_problem_desc *p, int64_t m) {
     L.nch = (int)((m + kSegChunk - 1) / kSegChunk);
     L.ntiles_scan = (int)((m + 2047) / 2048);
     L.nb_core = core_grad_blocks(m);
-    L.nb_fact = factor_grad_blocks((int32_t)m);
+    L.nb_fact = factor_grad_blocks(L.sh, (int32_t)m);
     L.nb_eval = eval_blocks(m);
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -1512,7 +1513,7 @@ MbLayout mb_layout(const ft_problem_desc *p, int64_t m) {
     L.counts = take(sizeof(uint32_t) * N * kRadix * L.tps);
     L.xcap = cross_capacity(m);
     L.xlist = take(sizeof(int4) * N * L.xcap);
-    L.pcap = part_capacity(m);
+    L.pcap = part_capacity(m, L.sh.J4);
     L.plist = take(sizeof(int4) * N * L.pcap);
     L.P = take(sizeof(float) * N * L.pcap * J4);
     L.xcount = take(sizeof(int32_t) * N * kXCounts);
@@ -1719,6 +1720,7 @@ static ft_status mb_backward_run(
     sa.scale = grad_out_dev;
     {
         CrossArgs cx{};
+        cx.J4 = L.sh.J4;
         cx.N = N;
         cx.nnz = m;
         cx.M = m;

@@ -42,8 +42,20 @@ constexpr int kSegChunk = 64;
 constexpr int kSmallCross = 256;      // crossing rows up to this many samples
                                       // are reduced by one wave
 constexpr int kSegWaves = 4;          // waves per row-reduction block
-constexpr int kSplitRows = 16384;     // crossing rows of more samples are
-constexpr int kPartRows = 2048;       // summed in parts of kPartRows
+// A crossing row whose gradient rows hold more than kSplitFloats floats is
+// summed in parts of kPartFloats floats (one block each) and the parts are
+// combined; in samples that is split_rows(J4) and part_rows(J4), so the
+// bytes one block reads stay the same at every row width.
+#ifndef FT_SPLIT_FLOATS
+#define FT_SPLIT_FLOATS 262144
+#endif
+#ifndef FT_PART_FLOATS
+#define FT_PART_FLOATS 32768
+#endif
+constexpr int kSplitFloats = FT_SPLIT_FLOATS;
+constexpr int kPartFloats = FT_PART_FLOATS;
+inline __host__ __device__ int split_rows(int J4) { return kSplitFloats / J4; }
+inline __host__ __device__ int part_rows(int J4) { return kPartFloats / J4; }
 constexpr int kXCounts = 4;           // per minibatch and mode: short rows,
                                       // long rows, parts, multi-part rows
 
@@ -145,7 +157,7 @@ struct FactorArgs {
 };
 hipError_t launch_factor_grad(const Shape &sh, const FactorArgs &a, int *nblocks,
                               hipStream_t s);
-int factor_grad_blocks(int32_t m);
+int factor_grad_blocks(const Shape &sh, int32_t m);
 // The same outputs with the contractions on vector FP32 FMAs (one sample
 // per lane), for the matrix-core ablation; FP32 only (factor_valu_supported).
 bool factor_valu_supported(const Shape &sh);
@@ -179,7 +191,7 @@ struct SegArgs {
     // xlist[n][0..) as (first, end, row, 0) and xcount[kXCounts n + 1]
     // longer rows fill xlist[n][xcap-1..] downwards as (first, end, row,
     // first part). A long row is summed in one part, or in
-    // ceil(count / kPartRows) parts when count > kSplitRows;
+    // ceil(count / part_rows(J4)) parts when count > split_rows(J4);
     // plist[n][0 .. xcount[kXCounts n + 2]) = (first, end, row, parts of
     // the row); rows of one part are finished at once, the others leave
     // partial sums in P[n][part][J4] for the combine kernel.
@@ -232,15 +244,16 @@ struct CrossArgs {
     int pcap;
     int32_t *xcount;                  // [nseg][N][kXCounts]
     int grid_cap;                     // > 0: at most this many workgroups
+    int J4;                           // row width (sets the part sizes)
 };
 hipError_t launch_crossing_segments(const CrossArgs &c, hipStream_t s);
 inline int cross_capacity(int64_t m) {
     const int64_t ch = (m + kSegChunk - 1) / kSegChunk;
     return ch > 1 ? (int)(ch - 1) : 1;
 }
-// sum over the long rows of ceil(count / kPartRows) <= rows + m / kPartRows
-inline int part_capacity(int64_t m) {
-    return cross_capacity(m) + (int)(m / kPartRows) + 1;
+// sum over the long rows of ceil(count / part) <= rows + m / part
+inline int part_capacity(int64_t m, int J4) {
+    return cross_capacity(m) + (int)(m / part_rows(J4)) + 1;
 }
 
 hipError_t launch_sum_blocks(const double *part, int nper, int ngroups,

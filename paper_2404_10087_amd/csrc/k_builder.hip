@@ -458,7 +458,7 @@ __global__ __launch_bounds__(kSortThreads) void sort_downsweep_kernel(
 // its end by a galloping search, and lists (first, end, row). Rows of at
 // most kSmallCross samples are listed from the front of the minibatch's
 // list, longer ones from the back together with their first part, and every
-// long row is cut into parts of kPartRows samples listed in plist. Each
+// long row is cut into parts of part_rows(J4) samples listed in plist. Each
 // class is in edge order: slots and part offsets come from block scans
 // (wave ballots and shuffle scans, then wave totals in LDS), so no atomics
 // and the lists are the same on every run.
@@ -511,9 +511,10 @@ __device__ __forceinline__ void crossing_one(const CrossArgs &c, int b,
         const bool small = flag && end - first <= kSmallCross;
         const bool large = flag && !small;
         const int cnt = end - first;
+        const int prows = part_rows(c.J4);
         const int parts = !large ? 0
-                          : (cnt > kSplitRows ? (cnt + kPartRows - 1) / kPartRows
-                                              : 1);
+                          : (cnt > split_rows(c.J4) ? (cnt + prows - 1) / prows
+                                                    : 1);
         // inclusive scan of the part counts over the wave
         int pincl = parts;
 #pragma unroll
@@ -541,7 +542,7 @@ __device__ __forceinline__ void crossing_one(const CrossArgs &c, int b,
             const int p0 = pp + pincl - parts;
             list[c.xcap - 1 - (pl + __popcll(bl & lt))] =
                 make_int4(first, end, (int)row, p0);
-            const int span = parts == 1 ? cnt : kPartRows;   // whole row
+            const int span = parts == 1 ? cnt : prows;   // whole row
             for (int j = 0; j < parts; ++j) {
                 const int f = first + j * span;
                 const int e = f + span < end ? f + span : end;

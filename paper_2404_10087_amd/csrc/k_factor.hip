@@ -28,14 +28,41 @@
 namespace ft {
 
 constexpr int kFactorThreads = 256;
-constexpr int kFactorMaxBlocks = 2048;
+#ifndef FT_FACTOR_MAX_BLOCKS
+#define FT_FACTOR_MAX_BLOCKS 2048
+#endif
+constexpr int kFactorMaxBlocks = FT_FACTOR_MAX_BLOCKS;
+// Grid cap for shapes whose B operands live in LDS (large N J R): each block
+// first stages B and builds the operand words (tens of KB of LDS writes), so
+// fewer blocks that loop over more tiles spend less of their time on it.
+#ifndef FT_FACTOR_LDS_CAP
+#define FT_FACTOR_LDS_CAP 2048
+#endif
+constexpr int kFactorLdsCap = FT_FACTOR_LDS_CAP;
 constexpr int kFactorTilesPerWave = 1;
 
-int factor_grad_blocks(int32_t m) {
+// Operand words per lane of the factor tile (FactorTile::OPW), from the
+// padded shape: the A-operand fragments of B^T (FP32: KQ words; BF16: two
+// per four entries; FP8: two per eight entries plus the scale, 8-byte
+// aligned) for every mode and column block, and the FP32 B fragments.
+constexpr int factor_operand_words(int N, int J4, int R16, int prec) {
+    const int KQ = J4 / 4, RB = R16 / 16, JB = (KQ + 3) / 4;
+    const int cfw = prec == kBF16 ? 2 * ((KQ + 3) / 4)
+                    : prec == kFP8 ? 2 * ((KQ + 7) / 8) + 2
+                                   : KQ;
+    return N * RB * cfw + N * JB * RB * 4;
+}
+static int factor_operand_words(const Shape &sh) {
+    return factor_operand_words(sh.N, sh.J4, sh.R16, sh.prec);
+}
+
+int factor_grad_blocks(const Shape &sh, int32_t m) {
     int ntiles = (m + 15) / 16;
     int blocks = (ntiles + 4 * kFactorTilesPerWave - 1) /
                  (4 * kFactorTilesPerWave);
-    if (blocks > kFactorMaxBlocks) blocks = kFactorMaxBlocks;
+    const int cap = factor_operand_words(sh) > 48 ? kFactorLdsCap
+                                                  : kFactorMaxBlocks;
+    if (blocks > cap) blocks = cap;
     return blocks < 1 ? 1 : blocks;
 }
 
@@ -55,6 +82,8 @@ struct FactorTile {
     static constexpr int CFW = sizeof(ColFrag<KQ, P>) / 4;
     static constexpr int OPW = N * RB * CFW + N * JB * RB * 4;
     static constexpr bool kLdsOps = OPW > 48;
+    static_assert(OPW == factor_operand_words(N, J4, R16, P),
+                  "the grid cap's operand count must match the tile's");
     int q, c, lane;
     ColFrag<KQ, P> bf[N][RB];
     float bb[N][JB][RB][4];
@@ -232,8 +261,9 @@ __device__ __forceinline__ void stage_B(const float *const *B, float *sB,
     __syncthreads();
 }
 
-// Each wave sweeps kFactorTilesPerWave tiles and issues the next tile's
-// index and row loads before the current tile's arithmetic.
+// Each wave sweeps its tiles with the next tile's loads in flight: its
+// indices are requested before the current tile's contraction and its rows
+// after it.
 // Waves per SIMD the register allocator is asked to reach. Without a hint
 // it reserves accumulator registers apart and lands one wave lower on most
 // shapes; two is reached by every shape without spilling or scratch
@@ -284,13 +314,24 @@ factor_grad_kernel(
 #pragma unroll
         for (int n = 0; n < N; ++n) arow[n] = arow_n[n];
         const float x = x_n;
-        if (tile + nwaves < ntiles) {
+        // the next tile's indices are requested before this tile's
+        // contraction and its rows after it, so neither load's latency
+        // stalls the matrix cores
+        const bool more = tile + nwaves < ntiles;
+        if (more) {
             const int pn = (tile + nwaves) * 16 + tl.c;
             const int psn = pn < a.m ? pn : a.m - 1;
-            tl.gather(a, psn, rows_n, arow_n);
+#pragma unroll
+            for (int n = 0; n < N; ++n) rows_n[n] = a.idx[n][psn];
             x_n = a.val[psn];
         }
         const float xh = tl.contract_rows(arow);
+        if (more) {
+#pragma unroll
+            for (int n = 0; n < N; ++n)
+                arow_n[n].load(RowSrc{a.A[n], a.A16[n], a.A8[n], a.As[n]},
+                               rows_n[n], T::J4, tl.q);
+        }
         const float r = valid ? xh - x : 0.f;
         if (valid && tl.q == 0) loss += 0.5 * (double)r * (double)r;
 #pragma unroll
@@ -571,7 +612,7 @@ static hipError_t launch_fg_j(const Shape &sh, const FactorArgs &a, int blocks,
 
 hipError_t launch_factor_grad(const Shape &sh, const FactorArgs &a, int *nblocks,
                               hipStream_t s) {
-    const int blocks = factor_grad_blocks(a.m);
+    const int blocks = factor_grad_blocks(sh, a.m);
     *nblocks = blocks;
     switch (sh.N) {
     case 2: return launch_fg_j<2>(sh, a, blocks, s);
@@ -702,8 +743,9 @@ __device__ __forceinline__ void finish_row(const SegArgs &a, int n,
 // One launch, three kinds of blocks (kSegWaves waves each), longest work
 // first so that it starts at once:
 //  * long crossing rows (blocks [0, large_blocks)): one block per row of
-//    more than kSmallCross samples, or, for a row of more than kSplitRows,
-//    one block per part of kPartRows samples; a row of one part is finished
+//    more than kSmallCross samples, or, for a row of more than
+//    split_rows(J4), one block per part of part_rows(J4) samples; a row of
+//    one part is finished
 //    at once, the others leave part sums for seg_combine_kernel;
 //  * chunks (the next chunk_blocks): one wave per chunk of 64 sorted
 //    samples of one mode; lane l holds sample i0 + l with its whole gradient
@@ -899,8 +941,8 @@ __global__ __launch_bounds__(kSegThreads) void seg_combine_kernel(SegArgs a) {
     if (n == a.N) return;                            // wave-uniform
     const int4 e = a.xlist[n][a.xcap - 1 - k];       // (first, end, row, p0)
     const int cnt = e.y - e.x;
-    if (cnt <= kSplitRows) return;                   // finished in one part
-    const int parts = (cnt + kPartRows - 1) / kPartRows;
+    if (cnt <= split_rows(J4)) return;               // finished in one part
+    const int parts = (cnt + part_rows(J4) - 1) / part_rows(J4);
     float acc[J4];
 #pragma unroll
     for (int q = 0; q < J4; ++q) acc[q] = 0.f;

@@ -67,7 +67,7 @@ def test_backward_matches_fp64_finite_differences():
                                         (3, 5, (40, 30, 20, 10), 3000),
                                         # rows of ~30,000 samples, summed
                                         # in several parts
-                                        (8, 16, (2000, 1500, 4), 70000),
+                                        (16, 16, (2000, 1500, 4), 70000),
                                         # order 7: A rows padded to 16
                                         (12, 16, (9, 8, 7, 6, 7, 8, 9),
                                          3000)])

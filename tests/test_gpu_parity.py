@@ -61,7 +61,7 @@ W = {
     # rows of ~20,000-30,000 samples per minibatch: long crossing rows
     # summed in several parts and combined
     "hot": synth.get("c0", name="hot", dims=(2000, 1500, 4), nnz=250_000,
-                     J=8, R=16, M=65536, index_dist="zipf", zipf_s=1.1,
+                     J=16, R=16, M=65536, index_dist="zipf", zipf_s=1.1,
                      row_mean=True, init_a_std=0.3, init_b_std=0.3),
 }
 
@@ -381,19 +381,36 @@ def test_hogwild_fast_mode_tracks_sequential_tiles():
     assert ft.rmse(FT_TEST) == pytest.approx(ormse, rel=0.02)
 
 
-def test_hogwild_fast_mode_on_skewed_rows_needs_small_steps():
-    """On a small Zipf instance every tile runs at once, so a hot row takes
-    thousands of steps computed from the same stale value (staleness grows
-    with concurrency and skew). With a step small enough for that, the fast
-    mode stays finite and lowers the test RMSE."""
+@pytest.mark.parametrize("lr", [1e-3, 3e-3])
+def test_hogwild_fast_mode_on_skewed_rows_tracks_sequential_tiles(lr):
+    """Zipf(1.2) rows (the hottest rows appear in hundreds of tiles of one
+    epoch): the fast mode runs every tile at once, so a hot row takes steps
+    computed from stale values; the oracle runs the same 16-sample tiles one
+    after another (M = 16, summed rows). Statistical tolerance: after three
+    alternating epochs the test RMSE is within 1% of the oracle's (measured
+    0.3-0.4% at these steps, which move the RMSE by 5-7%), and the epoch
+    improves on the initial point like the oracle's."""
     w = W["zipf"]
     ft, T, A0, B0 = setup(w)
-    ft.set_options(deterministic=0, row_scale=0, lr_A=1e-5)
+    ft.set_options(deterministic=0, row_scale=0, lr_A=lr)
+    A, B = f64(A0), f64(B0)
+    tv = T.train_val.astype(np.float64)
+    sv = T.test_val.astype(np.float64)
     r0 = ft.rmse(FT_TEST)
-    for _ in range(3):
+    for ep in range(3):
+        p = perm_for(w, T, ep)
+        ft.set_epoch_order(p)
         assert np.all(np.isfinite(ft.epoch_factors()))
         ft.epoch_core()
-    assert ft.rmse(FT_TEST) < r0
+        oracle.factor_epoch(A, B, T.train_idx, tv, p, 16, lr, w.lam_A, False)
+        oracle.core_epoch(A, B, T.train_idx, tv, w.lr_B, w.lam_B)
+    osse, _ = oracle.residual_stats(A, B, T.test_idx, sv)
+    ormse = np.sqrt(osse / len(sv))
+    g = ft.rmse(FT_TEST)
+    print(f"hogwild zipf lr {lr}: device {g:.6f} oracle {ormse:.6f} "
+          f"initial {r0:.6f}")
+    assert ormse < 0.97 * r0
+    assert g == pytest.approx(ormse, rel=0.01)
 
 
 def test_fast_mode_rejects_minibatch_not_multiple_of_tile():

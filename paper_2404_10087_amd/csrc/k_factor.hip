@@ -261,9 +261,9 @@ __device__ __forceinline__ void stage_B(const float *const *B, float *sB,
     __syncthreads();
 }
 
-// Each wave sweeps its tiles with the next tile's loads in flight: its
-// indices are requested before the current tile's contraction and its rows
-// after it.
+// Each wave sweeps its tiles and issues the next tile's index and row loads
+// before the current tile's arithmetic (requesting the rows only after the
+// current contraction measured no faster).
 // Waves per SIMD the register allocator is asked to reach. Without a hint
 // it reserves accumulator registers apart and lands one wave lower on most
 // shapes; two is reached by every shape without spilling or scratch
@@ -314,24 +314,13 @@ factor_grad_kernel(
 #pragma unroll
         for (int n = 0; n < N; ++n) arow[n] = arow_n[n];
         const float x = x_n;
-        // the next tile's indices are requested before this tile's
-        // contraction and its rows after it, so neither load's latency
-        // stalls the matrix cores
-        const bool more = tile + nwaves < ntiles;
-        if (more) {
+        if (tile + nwaves < ntiles) {
             const int pn = (tile + nwaves) * 16 + tl.c;
             const int psn = pn < a.m ? pn : a.m - 1;
-#pragma unroll
-            for (int n = 0; n < N; ++n) rows_n[n] = a.idx[n][psn];
+            tl.gather(a, psn, rows_n, arow_n);
             x_n = a.val[psn];
         }
         const float xh = tl.contract_rows(arow);
-        if (more) {
-#pragma unroll
-            for (int n = 0; n < N; ++n)
-                arow_n[n].load(RowSrc{a.A[n], a.A16[n], a.A8[n], a.As[n]},
-                               rows_n[n], T::J4, tl.q);
-        }
         const float r = valid ? xh - x : 0.f;
         if (valid && tl.q == 0) loss += 0.5 * (double)r * (double)r;
 #pragma unroll

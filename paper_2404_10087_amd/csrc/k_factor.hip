@@ -90,8 +90,9 @@ struct FactorTile {
     const uint32_t *ops;             // LDS operand words (kLdsOps)
     floatx4 D[N][RB];
 
-    // Operands from the (LDS-staged) B. With kLdsOps wave 0 writes them to
-    // ops_lds and the caller synchronises the block before the first tile.
+    // Operands from B (global memory, or the LDS copy the Hogwild kernel
+    // stages). With kLdsOps wave 0 writes them to ops_lds and the caller
+    // synchronises the block before the first tile.
     __device__ __forceinline__ void load_B(const float *const *Bm,
                                            uint32_t *ops_lds) {
         lane = threadIdx.x & 63;
@@ -261,9 +262,13 @@ __device__ __forceinline__ void stage_B(const float *const *B, float *sB,
     __syncthreads();
 }
 
-// Each wave sweeps its tiles and issues the next tile's index and row loads
-// before the current tile's arithmetic (requesting the rows only after the
-// current contraction measured no faster).
+// Each wave sweeps its tiles (one or two per wave at the large shapes) and
+// gathers each tile's rows when it starts it; the hardware hides the gather
+// latency with the other waves. Holding the next tile's rows in registers
+// (a software prefetch) and staging B in LDS before building the operands
+// both cost registers or LDS that kept a wave per SIMD out, and measured
+// slower at order 4-5, J = R = 32 (without them, per minibatch: order 5 BF16
+// 98 -> 79 us, order 4 FP32 96 -> 82 us) and no faster elsewhere.
 // Waves per SIMD the register allocator is asked to reach. Without a hint
 // it reserves accumulator registers apart and lands one wave lower on most
 // shapes; two is reached by every shape without spilling or scratch
@@ -272,8 +277,9 @@ __device__ __forceinline__ void stage_B(const float *const *B, float *sB,
 // running beside it, and the epoch with it. Order 10 at J = 16, R = 32 needs
 // one wave per SIMD to stay in registers.
 constexpr int factor_waves(int N, int KQ, int RB, int) {
-    return N > kFullOrder && N * KQ * RB >= 80 ? 1 : 2;   // (order 10)
+    return N > kFullOrder && N * KQ * RB >= 80 ? 1 : 2;
 }
+
 
 template <int N, int KQ, int RB, int P>
 __global__ __launch_bounds__(kFactorThreads)
@@ -281,7 +287,6 @@ __attribute__((amdgpu_waves_per_eu(factor_waves(N, KQ, RB, P)))) void
 factor_grad_kernel(
     FactorArgs a, int ntiles) {
     using T = FactorTile<N, KQ, RB, P>;
-    __shared__ float sB[N * T::J4 * T::R16];
     __shared__ uint32_t sOps[T::kLdsOps ? T::OPW * 64 : 1];
     T tl;
     tl.q = (threadIdx.x & 63) >> 4;
@@ -289,36 +294,29 @@ factor_grad_kernel(
     double loss = 0.0;
     const int nwaves = gridDim.x * (kFactorThreads / 64);
     int tile = blockIdx.x * (kFactorThreads / 64) + (threadIdx.x >> 6);
-    int rows_n[N];
-    RowFrag<KQ, P> arow_n[N];
-    float x_n = 0.f;
-    // the first tile's gathers are issued before B is staged, so their
-    // latency overlaps the staging and its barrier
+    int rows[N];
+    RowFrag<KQ, P> arow[N];
+    float x = 0.f;
+    // the first tile's gathers are issued before the B operands are built,
+    // so their latency overlaps that and its barrier
     if (tile < ntiles) {
         const int p = tile * 16 + tl.c;
         const int ps = p < a.m ? p : a.m - 1;
-        tl.gather(a, ps, rows_n, arow_n);
-        x_n = a.val[ps];
+        tl.gather(a, ps, rows, arow);
+        x = a.val[ps];
     }
-    const float *sBm[N];
-    stage_B<N, T::J4 * T::R16>(a.B, sB, sBm);
-    tl.load_B(sBm, sOps);
+    tl.load_B(a.B, sOps);
     if constexpr (T::kLdsOps) __syncthreads();
-    for (; tile < ntiles; tile += nwaves) {
+    for (bool first = true; tile < ntiles; tile += nwaves, first = false) {
         const int p = tile * 16 + tl.c;
         const bool valid = p < a.m;
         uint32_t inv[N];
 #pragma unroll
         for (int n = 0; n < N; ++n) inv[n] = valid ? a.inv[n][p] : 0u;
-        RowFrag<KQ, P> arow[N];
-#pragma unroll
-        for (int n = 0; n < N; ++n) arow[n] = arow_n[n];
-        const float x = x_n;
-        if (tile + nwaves < ntiles) {
-            const int pn = (tile + nwaves) * 16 + tl.c;
-            const int psn = pn < a.m ? pn : a.m - 1;
-            tl.gather(a, psn, rows_n, arow_n);
-            x_n = a.val[psn];
+        if (!first) {
+            const int ps = valid ? p : a.m - 1;
+            tl.gather(a, ps, rows, arow);
+            x = a.val[ps];
         }
         const float xh = tl.contract_rows(arow);
         const float r = valid ? xh - x : 0.f;

@@ -787,6 +787,63 @@ __device__ __forceinline__ void sum_rows_strided(const SegArgs &a, int n,
         for (int q = 0; q < J4; ++q) acc[q] += __shfl_xor(acc[q], d);
 }
 
+// The same sum with coalesced loads, for row widths that divide 64 lanes
+// into whole rows (J4 = 4, 8, 16, 32): the count rows at `rows` are read as
+// one flat run of float4s, thread t taking float4s t, t + stride, ..., all of
+// them in column quad t mod (J4 / 4); a fixed butterfly adds the lanes of
+// each column quad (log2(64 / (J4 / 4)) steps on four floats instead of six
+// steps on J4), and every lane then takes the whole row by J4 shuffles.
+template <int J4>
+__device__ __forceinline__ void sum_rows_coalesced(const float *rows,
+                                                   int count, int t,
+                                                   int stride,
+                                                   float (&acc)[J4]) {
+    constexpr int Q = J4 / 4;
+    constexpr int U = 16;
+    const float4 *G4 = reinterpret_cast<const float4 *>(rows);
+    const int total = count * Q;
+    float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int i = t; i < total; i += stride * U) {
+        float4 v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int k = i + u * stride;
+            v[u] = k < total ? G4[k] : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            s.x += v[u].x;
+            s.y += v[u].y;
+            s.z += v[u].z;
+            s.w += v[u].w;
+        }
+    }
+#pragma unroll
+    for (int d = 32; d >= Q; d >>= 1) {
+        s.x += __shfl_xor(s.x, d);
+        s.y += __shfl_xor(s.y, d);
+        s.z += __shfl_xor(s.z, d);
+        s.w += __shfl_xor(s.w, d);
+    }
+#pragma unroll
+    for (int c = 0; c < Q; ++c) {
+        acc[4 * c] = __shfl(s.x, c);
+        acc[4 * c + 1] = __shfl(s.y, c);
+        acc[4 * c + 2] = __shfl(s.z, c);
+        acc[4 * c + 3] = __shfl(s.w, c);
+    }
+}
+
+template <int J4>
+__device__ __forceinline__ void sum_rows(const SegArgs &a, int n, int4 se,
+                                         int t, int stride, float (&acc)[J4]) {
+    if constexpr ((J4 & (J4 - 1)) == 0)
+        sum_rows_coalesced<J4>(a.G + ((int64_t)n * a.m + se.x) * J4,
+                               se.y - se.x, t, stride, acc);
+    else
+        sum_rows_strided<J4>(a, n, se, t, stride, acc);
+}
+
 // Entry k of one class (cls 0: short rows, 1: long rows, 2: long-row
 // parts) over the modes in order: returns the mode (N if k is past the last
 // entry) and leaves the index within that mode's class in k.
@@ -829,7 +886,7 @@ __global__ __launch_bounds__(kSegThreads) void seg_reduce_kernel(
         if (n == a.N) return;
         const int4 pt = a.plist[n][j];        // (first, end, row, parts)
         float acc[J4];
-        sum_rows_strided<J4>(a, n, pt, t, kSegThreads, acc);
+        sum_rows<J4>(a, n, pt, t, kSegThreads, acc);
         if (lane == 0)
 #pragma unroll
             for (int q = 0; q < J4; ++q) red[w][q] = acc[q];
@@ -853,7 +910,7 @@ __global__ __launch_bounds__(kSegThreads) void seg_reduce_kernel(
         if (n == a.N) return;                         // wave-uniform
         const int4 se = a.xlist[n][k];
         float acc[J4];
-        sum_rows_strided<J4>(a, n, se, lane, 64, acc);
+        sum_rows<J4>(a, n, se, lane, 64, acc);
         if (lane == 0)
             finish_row<J4>(a, n, (uint32_t)se.z, acc, se.y - se.x, se.x);
         return;
@@ -931,19 +988,23 @@ __global__ __launch_bounds__(kSegThreads) void seg_combine_kernel(SegArgs a) {
     if (cnt <= split_rows(J4)) return;               // finished in one part
     const int parts = (cnt + part_rows(J4) - 1) / part_rows(J4);
     float acc[J4];
-#pragma unroll
-    for (int q = 0; q < J4; ++q) acc[q] = 0.f;
     const float *P = a.P + ((int64_t)n * a.pcap + e.w) * J4;
-    for (int i = lane; i < parts; i += 64) {
-        float g[J4];
-        load_row_part<J4>(P + (int64_t)i * J4, g);
+    if constexpr ((J4 & (J4 - 1)) == 0) {
+        sum_rows_coalesced<J4>(P, parts, lane, 64, acc);
+    } else {
 #pragma unroll
-        for (int q = 0; q < J4; ++q) acc[q] += g[q];
+        for (int q = 0; q < J4; ++q) acc[q] = 0.f;
+        for (int i = lane; i < parts; i += 64) {
+            float g[J4];
+            load_row_part<J4>(P + (int64_t)i * J4, g);
+#pragma unroll
+            for (int q = 0; q < J4; ++q) acc[q] += g[q];
+        }
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1)
+#pragma unroll
+            for (int q = 0; q < J4; ++q) acc[q] += __shfl_xor(acc[q], d);
     }
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1)
-#pragma unroll
-        for (int q = 0; q < J4; ++q) acc[q] += __shfl_xor(acc[q], d);
     if (lane == 0) finish_row<J4>(a, n, (uint32_t)e.z, acc, e.y - e.x, e.x);
 }
 

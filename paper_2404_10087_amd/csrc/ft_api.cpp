@@ -733,7 +733,7 @@ static ft_status build_minibatches(ft_handle *h, EpochBufs &E, hipStream_t s,
     const int tps = (int)((std::min<int64_t>(M, nnz) + kSortTile - 1) / kSortTile);
     const size_t nx = (size_t)nseg * h->N * kXCounts;
     HIPCHK(h, ensure(&E.counts, &E.counts_cap,
-                     (size_t)h->N * nseg * kRadix * tps));
+                     sort_counts_words(h->N, nseg, tps)));
     const int xcap = cross_capacity(std::min<int64_t>(M, nnz));
     const int pcap = part_capacity(std::min<int64_t>(M, nnz), h->sh.J4);
     HIPCHK(h, ensure(&E.xlist, &E.xlist_cap, (size_t)nseg * h->N * xcap));
@@ -863,25 +863,30 @@ static ft_status acquire_epoch(ft_handle *h) {
     return prepare(h);
 }
 
-// Build the next epoch's set on the builder stream (it only reads the
-// training records; the set it overwrites belonged to the finished epoch).
-// Its kernels run as small persistent grids so that the current epoch's
-// latency-bound minibatch kernels keep most of the workgroup slots.
-constexpr int kAheadGrid = 256;
-static ft_status build_ahead(ft_handle *h) {
+// Build the set of factor epoch `ep` on the builder stream (it only reads
+// the training records; the set it overwrites belonged to a finished epoch,
+// and every epoch call returns synchronised). It is started when a core
+// phase begins: the core kernels are bound by the matrix cores and leave
+// room beside them, while the minibatch kernels of a factor phase are
+// latency-bound and lose far more to a builder running beside them (at
+// order 5, J = R = 32, 200M nonzeros: epoch 215 ms with the builder beside
+// the factor phase on a small grid, 200 ms building serially before it,
+// 180 ms beside the core phase on a full grid).
+static ft_status build_ahead(ft_handle *h, uint64_t ep) {
     if (!h->opt.reshuffle_each_epoch || h->use_user_perm) return FT_OK;
     if (!h->bstream)
         HIPCHK(h, hipStreamCreateWithFlags(&h->bstream, hipStreamNonBlocking));
     EpochBufs &A = h->eb[h->cur ^ 1];
+    if (A.valid && A.epoch == ep && A.M == h->opt.minibatch &&
+        A.seed == h->opt.shuffle_seed && A.gen == h->train_gen)
+        return FT_OK;                    // built (or being built) already
     if (!A.perm) {
         ft_status st = alloc_epoch_bufs(h, A);
         if (st != FT_OK) return st;
     }
     ft_status st = counts_ready(h, A);   // an unused earlier build of A
     if (st != FT_OK) return st;
-    // the set was last read by a finished epoch (every epoch call returns
-    // synchronised), so the builder stream may overwrite it now
-    return build_epoch(h, A, h->epoch + 1, h->bstream, kAheadGrid);
+    return build_epoch(h, A, ep, h->bstream);
 }
 
 extern "C" ft_status ft_prepare_epoch(ft_handle *h) {
@@ -1053,10 +1058,6 @@ extern "C" ft_status ft_epoch_factors(ft_handle *h, double *mb_loss) {
         st = run_minibatch(h, b, 1, h->mb_part + b * nper, nullptr, nullptr);
         if (st != FT_OK) return st;
     }
-    // the next epoch's order, permutation and sort run beside this epoch's
-    // minibatches
-    st = build_ahead(h);
-    if (st != FT_OK) return st;
     HIPCHK(h, launch_sum_blocks(h->mb_part, nper, (int)nmb, h->mb_loss,
                                 h->stream));
     std::vector<double> losses((size_t)nmb);
@@ -1206,6 +1207,12 @@ extern "C" ft_status ft_epoch_core(ft_handle *h, double *loss) {
     const int64_t nnz = h->nnz[FT_TRAIN];
     if (nnz < 1) return fail(h, FT_ESTATE, "no training set");
     double l = 0.0;
+    // the next factor epoch's order, permutation and sort run beside this
+    // core phase
+    if (h->opt.deterministic) {
+        ft_status st = build_ahead(h, h->epoch);
+        if (st != FT_OK) return st;
+    }
     if (h->opt.core_step == FT_CORE_PER_EPOCH) {
         ft_status st = core_pass(h, h->idx[FT_TRAIN], h->val[FT_TRAIN], nnz, 1,
                                  nullptr, h->scal);
@@ -1510,7 +1517,7 @@ MbLayout mb_layout(const ft_problem_desc *p, int64_t m) {
     L.sv0 = take(sizeof(uint32_t) * N * m);
     L.sv1 = take(sizeof(uint32_t) * N * m);
     L.inv = take(sizeof(uint32_t) * N * m);
-    L.counts = take(sizeof(uint32_t) * N * kRadix * L.tps);
+    L.counts = take(sizeof(uint32_t) * sort_counts_words((int)N, 1, L.tps));
     L.xcap = cross_capacity(m);
     L.xlist = take(sizeof(int4) * N * L.xcap);
     L.pcap = part_capacity(m, L.sh.J4);

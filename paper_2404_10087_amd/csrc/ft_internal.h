@@ -128,10 +128,16 @@ struct SortPass {
     uint32_t *val_out[kMaxOrder];   // nullptr: positions not written
     uint32_t *inv_out[kMaxOrder];   // final pass only (else nullptr):
                                     // inv[seg + pos] = sorted index in seg
-    uint32_t *counts;    // [N][nseg][tiles_per_seg][kRadix]
+    // [N][nseg][tiles_per_seg + 1][kRadix]: per tile the digit counts (the
+    // upsweep), then the counts in the segment's earlier tiles; the extra
+    // last row holds the segment's digit starts
+    uint32_t *counts;
     int grid_cap;        // > 0: at most this many workgroups (background)
 };
 hipError_t launch_sort_pass(const SortPass &p, hipStream_t s);
+inline size_t sort_counts_words(int N, int nseg, int tiles_per_seg) {
+    return (size_t)N * nseg * (tiles_per_seg + 1) * kRadix;
+}
 // 8-bit LSD passes that sort row ids 0 .. dims - 1 (at least one)
 inline int radix_passes(int64_t dims) {
     int bits = 0;

@@ -269,11 +269,12 @@ __host__ __device__ inline int sort_grid(const SortPass &p) {
     return groups * kXcds * p.tiles_per_seg;
 }
 
-// counts of tile tb of segment b, mode n: kRadix consecutive words
+// counts of tile tb of segment b, mode n: kRadix consecutive words (tb =
+// tiles_per_seg: the segment's digit starts)
 __device__ __forceinline__ uint32_t *counts_at(const SortPass &p, int n, int b,
                                                int tb) {
-    return p.counts + (((int64_t)n * p.nseg + b) * p.tiles_per_seg + tb) *
-                          kRadix;
+    return p.counts +
+           (((int64_t)n * p.nseg + b) * (p.tiles_per_seg + 1) + tb) * kRadix;
 }
 
 // Digit histogram of tile id L (sort_tile_of); every wave counts into its
@@ -315,10 +316,53 @@ __global__ __launch_bounds__(kSortThreads) void sort_upsweep_kernel(SortPass p) 
     }
 }
 
+// Offsets of every (mode, segment) of the pass, one block each: thread d
+// replaces the upsweep's count of digit d in every tile by the count in the
+// tiles before it (an exclusive scan over the tiles, eight loads in flight),
+// and the segment's totals are scanned over the digits into its digit
+// starts. The downsweep then reads two words per digit instead of a column
+// of counts per tile.
+__global__ __launch_bounds__(kSortThreads) void sort_scan_kernel(SortPass p) {
+    __shared__ uint32_t sc[kRadix];
+    const int tid = threadIdx.x;
+    for (int sb = blockIdx.x; sb < p.N * p.nseg; sb += gridDim.x) {
+        const int n = sb / p.nseg, b = sb % p.nseg;
+        const TileInfo t = tile_info(p, b, 0);
+        uint32_t *c = counts_at(p, n, b, 0) + tid;
+        uint32_t run = 0;
+        int k = 0;
+        for (; k + 8 <= t.tiles_in_seg; k += 8) {
+            uint32_t v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = c[(int64_t)(k + u) * kRadix];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                c[(int64_t)(k + u) * kRadix] = run;
+                run += v[u];
+            }
+        }
+        for (; k < t.tiles_in_seg; ++k) {
+            const uint32_t v = c[(int64_t)k * kRadix];
+            c[(int64_t)k * kRadix] = run;
+            run += v;
+        }
+        sc[tid] = run;
+        __syncthreads();
+        for (int off = 1; off < kRadix; off <<= 1) {
+            const uint32_t v = tid >= off ? sc[tid - off] : 0u;
+            __syncthreads();
+            sc[tid] += v;
+            __syncthreads();
+        }
+        counts_at(p, n, b, p.tiles_per_seg)[tid] = sc[tid] - run;
+        __syncthreads();
+    }
+}
+
 // Stable scatter of tile id L (sort_tile_of), staged in LDS. The global
-// start of digit d for this tile is the exclusive scan over digits of the
-// segment's digit totals plus the counts of d in the tiles before this one
-// (read from the upsweep's histograms). The tile is then ordered by digit
+// start of digit d for this tile is the segment's start of d plus the count
+// of d in the tiles before this one (both from the scan kernel). The tile
+// is then ordered by digit
 // locally (the rank of an element among equal digits
 // is the number of equal digits before it in the tile, taken round by round
 // -- 256 consecutive elements per round -- from wave match masks and per-wave
@@ -346,35 +390,8 @@ __device__ __forceinline__ void downsweep_tile(const SortPass &p, int L) {
     uint32_t *vout = p.val_out[n] ? p.val_out[n] + t.seg_start : nullptr;
 
     uint32_t key[kSortRounds], val[kSortRounds];
-    {
-        uint32_t before = 0, total = 0;
-        const uint32_t *c = counts_at(p, n, b, 0) + tid;
-        int k = 0;
-        for (; k + 8 <= t.tiles_in_seg; k += 8) {
-            uint32_t v[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) v[u] = c[(int64_t)(k + u) * kRadix];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                total += v[u];
-                before += k + u < tb ? v[u] : 0u;
-            }
-        }
-        for (; k < t.tiles_in_seg; ++k) {
-            const uint32_t v = c[(int64_t)k * kRadix];
-            total += v;
-            before += k < tb ? v : 0u;
-        }
-        lstart[tid] = total;
-        __syncthreads();
-        for (int off = 1; off < kRadix; off <<= 1) {
-            const uint32_t v = tid >= off ? lstart[tid - off] : 0u;
-            __syncthreads();
-            lstart[tid] += v;
-            __syncthreads();
-        }
-        base[tid] = lstart[tid] - total + before;
-    }
+    base[tid] = counts_at(p, n, b, p.tiles_per_seg)[tid] +
+                counts_at(p, n, b, tb)[tid];
     run[tid] = 0;
     __syncthreads();
 #pragma unroll
@@ -590,6 +607,12 @@ hipError_t launch_sort_pass(const SortPass &p, hipStream_t s) {
     dim3 g3(grid);
     hipLaunchKernelGGL(sort_upsweep_kernel, g3, dim3(kSortThreads), 0, s, p);
     hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    int sgrid = p.N * p.nseg;
+    if (p.grid_cap > 0 && sgrid > p.grid_cap) sgrid = p.grid_cap;
+    hipLaunchKernelGGL(sort_scan_kernel, dim3(sgrid), dim3(kSortThreads), 0, s,
+                       p);
+    e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(sort_downsweep_kernel, g3, dim3(kSortThreads), 0, s, p);
     return hipGetLastError();

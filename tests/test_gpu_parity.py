@@ -541,7 +541,8 @@ def test_fp8_needs_verify_mode():
 # ----------------------------------------------------------------- builder ahead
 def test_epoch_builder_ahead_matches_injected_orders():
     """The next epoch's order, permutation and sort are built on a second
-    stream while the current epoch trains. Epochs that use those sets give
+    stream while the current epoch's core phase runs. Epochs that use those
+    sets give
     bitwise the same parameters as epochs whose orders (the same
     counter-based permutations, from their definition) are injected one by
     one and built in line."""

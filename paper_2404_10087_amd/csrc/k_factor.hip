@@ -310,14 +310,16 @@ factor_grad_kernel(
     for (bool first = true; tile < ntiles; tile += nwaves, first = false) {
         const int p = tile * 16 + tl.c;
         const bool valid = p < a.m;
-        uint32_t inv[N];
-#pragma unroll
-        for (int n = 0; n < N; ++n) inv[n] = valid ? a.inv[n][p] : 0u;
+        const int ps = valid ? p : a.m - 1;
         if (!first) {
-            const int ps = valid ? p : a.m - 1;
             tl.gather(a, ps, rows, arow);
             x = a.val[ps];
         }
+        // sorted slots, read at a clamped index rather than under a branch:
+        // a branch around each load made it wait before the next one
+        uint32_t inv[N];
+#pragma unroll
+        for (int n = 0; n < N; ++n) inv[n] = a.inv[n][ps];
         const float xh = tl.contract_rows(arow);
         const float r = valid ? xh - x : 0.f;
         if (valid && tl.q == 0) loss += 0.5 * (double)r * (double)r;
@@ -400,12 +402,18 @@ __global__ __launch_bounds__(kFactorThreads) void hogwild_kernel(HogArgs a) {
                     g = sum;
                 }
                 const int j0 = 16 * jb + 4 * tl.q;
+                // the row's current entries, read by every lane from an
+                // in-bounds address before the branch (a read inside it
+                // would be waited for there, once per store)
+                float *ap = a.A[n] + (int64_t)rows[n] * T::J4 +
+                            (j0 < T::J4 ? j0 : T::J4 - 4);
+                const float4 av = *reinterpret_cast<const float4 *>(ap);
                 if (valid && leader && j0 < T::J4) {
-                    float *ap = a.A[n] + (int64_t)rows[n] * T::J4 + j0;
-#pragma unroll
-                    for (int v = 0; v < 4; ++v)
-                        unsafeAtomicAdd(ap + v, -a.lr * (g[v] + (float)cnt *
-                                                         a.lam * ap[v]));
+                    const float k = (float)cnt * a.lam;
+                    unsafeAtomicAdd(ap + 0, -a.lr * (g[0] + k * av.x));
+                    unsafeAtomicAdd(ap + 1, -a.lr * (g[1] + k * av.y));
+                    unsafeAtomicAdd(ap + 2, -a.lr * (g[2] + k * av.z));
+                    unsafeAtomicAdd(ap + 3, -a.lr * (g[3] + k * av.w));
                 }
             }
         }
@@ -922,9 +930,15 @@ __global__ __launch_bounds__(kSegThreads) void seg_reduce_kernel(
     const int i1 = min(i0 + kSegChunk, a.m);
     const bool valid = i < i1;
     const uint32_t *rows = a.rows[n];
-    const uint32_t row = valid ? rows[i] : 0xffffffffu;
-    const uint32_t before_chunk = i0 > 0 ? rows[i0 - 1] : 0xffffffffu;
-    const uint32_t after_chunk = i1 < a.m ? rows[i1] : 0xffffffffu;
+    // every load below is issued unconditionally from a clamped or dummy
+    // address and its value selected afterwards: a load under a branch is
+    // waited for inside the branch, which serialised the chunk's round trips
+    const uint32_t row_v = rows[min(i, i1 - 1)];
+    const uint32_t before_v = rows[max(i0 - 1, 0)];
+    const uint32_t after_v = rows[min(i1, a.m - 1)];
+    const uint32_t row = valid ? row_v : 0xffffffffu;
+    const uint32_t before_chunk = i0 > 0 ? before_v : 0xffffffffu;
+    const uint32_t after_chunk = i1 < a.m ? after_v : 0xffffffffu;
     const uint32_t below = __shfl_up(row, 1);
     const uint32_t above = __shfl_down(row, 1);
     const uint32_t last_row = __shfl(row, i1 - 1 - i0);
@@ -943,15 +957,20 @@ __global__ __launch_bounds__(kSegThreads) void seg_reduce_kernel(
     const bool in_crossing = (s == 0 && before_chunk == row) ||
                              (row == last_row && after_chunk == row);
     const bool finish = tail && !in_crossing;
+    const bool take = valid && !in_crossing;
+    // lanes that take nothing read the chunk's first gradient row (one
+    // line for all of them) and the first row of A
     float g[J4];
-    if (valid && !in_crossing) {
-        load_row_part<J4>(a.G + ((int64_t)n * a.m + i) * J4, g);
+    load_row_part<J4>(a.G + ((int64_t)n * a.m + (take ? i : i0)) * J4, g);
+#pragma unroll
+    for (int q = 0; q < J4; ++q) g[q] = take ? g[q] : 0.f;
+    float av[J4];
+    if (a.apply != 2) {
+        load_row_part<J4>(a.A[n] + (int64_t)(finish ? row : 0u) * J4, av);
     } else {
 #pragma unroll
-        for (int q = 0; q < J4; ++q) g[q] = 0.f;
+        for (int j = 0; j < J4; ++j) av[j] = 0.f;
     }
-    float av[J4];
-    if (finish) load_av<J4>(a, n, row, av);
 #pragma unroll
     for (int d = 1; d < 64; d <<= 1) {
         const bool take = lane - d >= s;

@@ -99,8 +99,9 @@ core_grad_kernel(CoreArgs a, int64_t ntiles) {
     // B-operands B[k = KQ*q + t][r = 16 rb + c]: the same in every wave.
     // Large sets (order 4-5 at J = R = 32) live in LDS, one copy per block
     // laid out [word][lane], written by wave 0 and read at each use (the
-    // lane index goes through an empty asm statement so the reads are not
-    // hoisted back into registers); small sets stay in registers.
+    // lane index goes through an empty asm statement once per tile so the
+    // reads are not hoisted back into registers but are scheduled freely
+    // within the tile); small sets stay in registers.
     constexpr int CFW = sizeof(ColFrag<KQ, P>) / 4;
     constexpr bool kLdsOps = N * RB * CFW > 32;
     __shared__ uint32_t sOps[kLdsOps ? N * RB * CFW * 64 : 1];
@@ -121,10 +122,10 @@ core_grad_kernel(CoreArgs a, int64_t ntiles) {
             }
     }
     if constexpr (kLdsOps) __syncthreads();
+    int lane_o = lane;
     auto operand = [&](int n, int rb) -> ColFrag<KQ, P> {
         if constexpr (kLdsOps) {
-            int l = lane;
-            asm volatile("" : "+v"(l));
+            const int l = lane_o;
             uint32_t w[CFW];
 #pragma unroll
             for (int i = 0; i < CFW; ++i)
@@ -153,6 +154,8 @@ core_grad_kernel(CoreArgs a, int64_t ntiles) {
     CoreTileIn<N, KQ, P> nxt;
     if (tile < ntiles) load_core_tile<N, KQ, P>(a, tile, q, c, nxt);
     for (; tile < ntiles; tile += nwaves) {
+        lane_o = lane;
+        asm volatile("" : "+v"(lane_o));
         const CoreTileIn<N, KQ, P> cur = nxt;
         if (tile + nwaves < ntiles)
             load_core_tile<N, KQ, P>(a, tile + nwaves, q, c, nxt);

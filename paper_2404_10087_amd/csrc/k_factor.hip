@@ -882,6 +882,55 @@ __device__ __forceinline__ float sum_waves(float (*red)[J4 + 1], int lane,
     return v;
 }
 
+// Data-parallel-primitive moves between lanes (no LDS): row_shr:d gives
+// lane l the value of lane l - d of its 16-lane row (0 where there is none);
+// row_bcast:15 gives rows 1 and 3 the value of the last lane of the row
+// before; row_bcast:31 gives rows 2 and 3 the value of lane 31.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float dpp_take(float x) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(
+        0, __float_as_int(x), CTRL, ROWS, 0xf, false));
+}
+
+// Inclusive segmented scan of the J4 values of every lane in lane order,
+// s being the first lane of the lane's segment: afterwards lane l holds the
+// sum over lanes s .. l. Hillis-Steele within each 16-lane row (shifts 1, 2,
+// 4, 8), then the rows are joined in order: row 1 takes row 0's last lane
+// and row 3 row 2's (row_bcast:15), then rows 2-3 take lane 31, which by
+// then covers rows 0-1 (row_bcast:31); a lane adds only inside its segment.
+// Every move is a DPP operand of the add, where shuffles through LDS cost a
+// crossbar round trip per value and step.
+template <int J4>
+__device__ __forceinline__ void seg_scan_dpp(float (&g)[J4], int lane,
+                                             int s) {
+    const int in_row = lane & 15, row0 = lane & ~15;
+    const bool t1 = in_row >= 1 && lane - 1 >= s;
+    const bool t2 = in_row >= 2 && lane - 2 >= s;
+    const bool t4 = in_row >= 4 && lane - 4 >= s;
+    const bool t8 = in_row >= 8 && lane - 8 >= s;
+    const bool t15 = (lane & 16) && s < row0;
+    const bool t31 = lane >= 32 && s < 32;
+    // one value at a time through all six steps (the step masks are
+    // shared), so no value waits in a register for the others
+#pragma unroll
+    for (int q = 0; q < J4; ++q) {
+        float x = g[q], t;
+        t = dpp_take<0x111, 0xf>(x);
+        if (t1) x += t;
+        t = dpp_take<0x112, 0xf>(x);
+        if (t2) x += t;
+        t = dpp_take<0x114, 0xf>(x);
+        if (t4) x += t;
+        t = dpp_take<0x118, 0xf>(x);
+        if (t8) x += t;
+        t = dpp_take<0x142, 0xa>(x);
+        if (t15) x += t;
+        t = dpp_take<0x143, 0xc>(x);
+        if (t31) x += t;
+        g[q] = x;
+    }
+}
+
 template <int KQ>
 __global__ __launch_bounds__(kSegThreads) void seg_reduce_kernel(
     SegArgs a, int chunk_blocks) {
@@ -943,12 +992,9 @@ __global__ __launch_bounds__(kSegThreads) void seg_reduce_kernel(
     const uint32_t above = __shfl_down(row, 1);
     const uint32_t last_row = __shfl(row, i1 - 1 - i0);
     const bool head = lane == 0 || row != below;
-    int s = head ? lane : 0;                      // first lane of my segment
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const int t2 = __shfl_up(s, d);
-        if (lane >= d) s = max(s, t2);
-    }
+    // first lane of my segment: the highest head at or below my lane
+    const uint64_t heads = __ballot(head) & ((2ull << lane) - 1ull);
+    const int s = 63 - __clzll(heads);
     const bool last_in_chunk = i == i1 - 1;
     const bool tail = valid && (last_in_chunk || above != row);
     // the chunk's first segment may continue from the previous chunk and
@@ -971,15 +1017,7 @@ __global__ __launch_bounds__(kSegThreads) void seg_reduce_kernel(
 #pragma unroll
         for (int j = 0; j < J4; ++j) av[j] = 0.f;
     }
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const bool take = lane - d >= s;
-#pragma unroll
-        for (int q = 0; q < J4; ++q) {
-            const float t2 = __shfl_up(g[q], d);
-            if (take) g[q] += t2;
-        }
-    }
+    seg_scan_dpp<J4>(g, lane, s);
     if (finish) finish_row_av<J4>(a, n, row, g, lane - s + 1, i0 + s, av);
 }
 

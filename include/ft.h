@@ -173,11 +173,10 @@ ft_status ft_num_minibatches(const ft_handle *h, int64_t *out);
  * at the minibatch start, and update every touched row (Eq. (12), scaled by
  * row_scale). mb_loss (NULL or [ceil(nnz/M)]) receives sum r^2/2 of every
  * minibatch, r = xhat - x. Advances the epoch counter. Returns after the
- * epoch's work is complete. With the device-side order and
- * reshuffle_each_epoch = 1 the order, permutation and sort of the NEXT epoch
- * are built on an internal second stream (non-blocking, default priority)
- * while this epoch's minibatches run; the next call uses them if the
- * options, seed and training set are unchanged, else rebuilds in line. In
+ * epoch's work is complete. It uses the order, permutation and sort built
+ * ahead by the preceding ft_epoch_core (see there) if they were built for
+ * this epoch with the current options, seed and training set, else builds
+ * them in line. In
  * the fast mode the tiles run concurrently with immediate per-sample steps
  * a <- a - lr_A (r B d + lambda_A a) (Eq. (12) applied per sample, Hogwild);
  * row_scale does not apply. */
@@ -199,7 +198,12 @@ ft_status ft_factor_minibatch(ft_handle *h, int64_t b, int32_t apply,
 /* One core epoch (Algorithm 5, or per-minibatch steps with
  * FT_CORE_PER_MINIBATCH): Grad^(n) = sum_s r_s a^(n)T d^(n) with A, B fixed,
  * then B^(n) <- B^(n) - lr_B (Grad^(n)/|Omega| + lambda_B B^(n)) for all n at
- * once. *loss (may be NULL) receives sum r^2/2 over the training set. */
+ * once. *loss (may be NULL) receives sum r^2/2 over the training set.
+ * In the verify mode with the device-side order and reshuffle_each_epoch = 1
+ * it first starts building the order, permutation and sort of the next
+ * factor epoch on an internal second stream (non-blocking, default
+ * priority), beside its own kernels; that build may still run when it
+ * returns, and the next ft_epoch_factors waits for it. */
 ft_status ft_epoch_core(ft_handle *h, double *loss);
 
 /* Core gradient only: Grad^(n) (J_n x R row-major, no regulariser) summed

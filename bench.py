@@ -275,6 +275,15 @@ def run_leg(name, w, T, A0, B0, args, precision, options):
                               "avg_us": round(1000 * v[1] / v[0], 3)}
                           for k, v in stats.items() if v[0]}
         out["profiled_epochs"] = 1 if hog else args.profile_steps
+        if not hog:
+            # the builder alone (in line on the library stream, full grids):
+            # during the timed epochs it runs beside the core phase, where
+            # its event times include the sharing
+            ft.prepare_epoch()
+            a = time.perf_counter()
+            for _ in range(2):
+                ft.prepare_epoch()
+            out["builder_alone_ms"] = 1000.0 * (time.perf_counter() - a) / 2
         if not hog and not args.no_oracle_check:
             log(f"{name}: oracle check")
             out["oracle_check"] = oracle_check(ft, w, T, args.test_slice)
@@ -461,6 +470,7 @@ def main():
         "builder_kernel_ms_per_epoch": sum(
             kf[x]["total_ms"] for x in ("order", "permute", "sort")
             if x in kf) / head["profiled_epochs"],
+        "builder_alone_ms_per_epoch": head.get("builder_alone_ms"),
         "test_rmse": head.get("test_rmse"),
         "test_rmse_after_epochs": head.get("test_rmse_after_epochs"),
         "oracle_check": head.get("oracle_check"),

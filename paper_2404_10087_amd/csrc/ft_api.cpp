@@ -702,7 +702,7 @@ static ft_status alloc_epoch_bufs(ft_handle *h, EpochBufs &E) {
 }
 
 static ft_status draw_order(ft_handle *h, EpochBufs &E, uint64_t epoch,
-                            uint64_t salt, hipStream_t s, int cap = 0) {
+                            uint64_t salt, hipStream_t s) {
     const int64_t nnz = h->nnz[FT_TRAIN];
     Launch L(h, FT_K_ORDER, s);
     if (h->use_user_perm) {
@@ -712,21 +712,20 @@ static ft_status draw_order(ft_handle *h, EpochBufs &E, uint64_t epoch,
         const uint64_t e = h->opt.reshuffle_each_epoch ? epoch : 0;
         const uint64_t key = h->opt.shuffle_seed ^
                              (0x9e3779b97f4a7c15ull * (2 * e + 1 + 2 * salt));
-        HIPCHK(h, launch_epoch_order(E.perm, nnz, key, s, cap));
+        HIPCHK(h, launch_epoch_order(E.perm, nnz, key, s));
     }
     return FT_OK;
 }
 
-static ft_status permute_streams(ft_handle *h, EpochBufs &E, hipStream_t s,
-                                int cap = 0) {
+static ft_status permute_streams(ft_handle *h, EpochBufs &E, hipStream_t s) {
     Launch L(h, FT_K_PERMUTE, s);
     HIPCHK(h, launch_permute(h->N, h->rec, record_words(h->N), E.perm,
-                             h->nnz[FT_TRAIN], E.pidx, E.pval, s, cap));
+                             h->nnz[FT_TRAIN], E.pidx, E.pval, s));
     return FT_OK;
 }
 
-static ft_status build_minibatches(ft_handle *h, EpochBufs &E, hipStream_t s,
-                                   int cap = 0) {
+static ft_status build_minibatches(ft_handle *h, EpochBufs &E,
+                                   hipStream_t s) {
     const int64_t nnz = h->nnz[FT_TRAIN];
     const int64_t M = h->opt.minibatch;
     const int nseg = (int)nminibatches(h);
@@ -755,7 +754,6 @@ static ft_status build_minibatches(ft_handle *h, EpochBufs &E, hipStream_t s,
     p.nseg = nseg;
     p.tiles_per_seg = tps;
     p.counts = E.counts;
-    p.grid_cap = cap;
     // each mode takes as many 8-bit passes as its own row ids need; a pass
     // sorts the modes that still have digits left (packed into slots)
     int passes[kMaxOrder], cur[kMaxOrder] = {}, max_passes = 1;
@@ -795,7 +793,6 @@ static ft_status build_minibatches(ft_handle *h, EpochBufs &E, hipStream_t s,
     cx.plist = E.plist;
     cx.pcap = pcap;
     cx.xcount = E.xcount;
-    cx.grid_cap = cap;
     cx.J4 = h->sh.J4;
     E.xcap = xcap;
     E.pcap = pcap;
@@ -811,11 +808,11 @@ static ft_status build_minibatches(ft_handle *h, EpochBufs &E, hipStream_t s,
 }
 
 static ft_status build_epoch(ft_handle *h, EpochBufs &E, uint64_t epoch,
-                             hipStream_t s, int cap = 0) {
+                             hipStream_t s) {
     E.valid = false;
-    ft_status st = draw_order(h, E, epoch, 0, s, cap);
-    if (st == FT_OK) st = permute_streams(h, E, s, cap);
-    if (st == FT_OK) st = build_minibatches(h, E, s, cap);
+    ft_status st = draw_order(h, E, epoch, 0, s);
+    if (st == FT_OK) st = permute_streams(h, E, s);
+    if (st == FT_OK) st = build_minibatches(h, E, s);
     if (st != FT_OK) return st;
     E.valid = true;
     E.epoch = epoch;

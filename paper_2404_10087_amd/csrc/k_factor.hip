@@ -744,11 +744,12 @@ __device__ __forceinline__ void finish_row(const SegArgs &a, int n,
 //    at once, the others leave part sums for seg_combine_kernel;
 //  * chunks (the next chunk_blocks): one wave per chunk of 64 sorted
 //    samples of one mode; lane l holds sample i0 + l with its whole gradient
-//    row. A segmented inclusive scan across the lanes (Hillis-Steele, steps
-//    1..32; a lane adds the value d lanes below when that lane belongs to its
-//    segment) leaves every row's sum in the lane of its last sample, which
-//    finishes the row -- unless the row's samples cross a chunk edge. The
-//    finishing lanes fetch their rows of A together with the gradient rows;
+//    row. A segmented inclusive scan across the lanes (seg_scan_dpp: DPP
+//    shifts within 16-lane rows, then row broadcasts; a lane adds only
+//    values of its own segment) leaves every row's sum in the lane of its
+//    last sample, which finishes the row -- unless the row's samples cross a
+//    chunk edge. The finishing lanes fetch their rows of A together with the
+//    gradient rows;
 //  * short crossing rows (the rest): one wave per row of at most kSmallCross
 //    samples, kSegWaves per block, from the front of the list.
 // A crossing row's threads sum its (contiguous) gradient rows with a fixed

@@ -479,7 +479,9 @@ __global__ __launch_bounds__(kSortThreads) void sort_downsweep_kernel(
 // class is in edge order: slots and part offsets come from block scans
 // (wave ballots and shuffle scans, then wave totals in LDS), so no atomics
 // and the lists are the same on every run.
-constexpr int kCrossThreads = 1024;
+// 256 threads: the list is built beside the core kernel, whose blocks leave
+// room for four-wave workgroups but not for sixteen-wave ones
+constexpr int kCrossThreads = 256;
 
 __device__ __forceinline__ void crossing_one(const CrossArgs &c, int b,
                                              int n) {
